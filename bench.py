@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Throughput of arc x constant-latitude intersections on one MI355X.
+
+A step is one sphint_arc_constlat call over the whole workload (every pair evaluated,
+counts/flags written, hits compacted), inputs already resident in HBM.  Default workload:
+10^7 ill-conditioned arcs in three equal parts (1e-10..1e-6 rad arcs; latitudes within
+1e-12 of an arc's apex or nadir; arcs within 1e-6 rad of a pole), one latitude per arc.
+The EFT step is the headline; the naive binary64 step runs on the same inputs beside it.
+
+Prints one JSON line.  Extra lines go to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+METRIC = "arc-latitude intersections/s (EFT vs naive FP64, ≤4·2^-53 err); p99 latency"
+HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+ALU_PEAK = 256 * 64 * 2.4e9  # binary64 lane operations/s: 256 CUs x 64 lanes x 2.4 GHz
+BYTES_PER_PAIR = 7 * 8 + 2   # x1, y1, z1, x2, y2, z2, z0 read; count + flags written
+BYTES_PER_HIT = 8 + 8 + 8 + 1  # x, y, pair, root
+EFT_OPS_PER_PAIR = 254       # algorithmic binary64 operations (arc part 161 + pair part 93)
+EFT_OPS_PER_HIT = 84         # two compensated dot products and two divisions per root
+NAIVE_OPS_PER_PAIR = 38
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_mode(torch, sphint, dev, mode, steps, warmup):
+    x1, y1, z1, x2, y2, z2, z0 = dev
+    n = len(z0)
+    out = sphint.Output(n)
+    for _ in range(warmup):
+        sphint.arc_constlat((x1, y1, z1), (x2, y2, z2), z0, mode=mode, out=out)
+    total = out.check()
+    timer = sphint.KernelTimer(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        timer.arm(k)
+        sphint.arc_constlat((x1, y1, z1), (x2, y2, z2), z0, mode=mode, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timer.disarm()
+    kms = timer.durations_ms()
+    timer.close()
+    total2 = out.check()
+    assert total2 == total
+    return dict(wall_s=t1 - t0, kernel_ms=kms, total=total, out=out)
+
+
+def latency_small(torch, sphint, inputs, reps=200):
+    """Per-call latency on the 1e5-arc uniform workload (host enqueue to completion)."""
+    P = inputs.uniform_arcs(100_000, seed_tag=0)
+    dev = [torch.from_numpy(a).cuda() for a in P.soa()]
+    out = sphint.Output(len(P))
+    lat = []
+    for r in range(reps + 10):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sphint.arc_constlat(tuple(dev[:3]), tuple(dev[3:6]), dev[6], mode="eft", out=out)
+        torch.cuda.synchronize()
+        if r >= 10:
+            lat.append((time.perf_counter() - t0) * 1e6)
+    lat.sort()
+    return dict(p50_us=lat[len(lat) // 2], p99_us=lat[int(len(lat) * 0.99) - 1], calls=reps)
+
+
+def cpu_baseline(P, inputs, sample):
+    """The oracle (exact predicates + 100-digit points) on a stratified sample, all workers."""
+    from oracle import batch as OB
+    idx = inputs.stratified_sample(P, sample // 3, seed=11)
+    S = P.take(idx)
+    workers = OB.default_workers()
+    t0 = time.perf_counter()
+    OB.exact(*S.soa(), workers=workers)
+    dt = time.perf_counter() - t0
+    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(S)} pairs, stratified over the 3 parts of the same workload "
+                      f"(exact integer predicates + 100-digit decimal points), {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--modes", default="eft,naive")
+    ap.add_argument("--cpu-sample", type=int, default=450_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a torch copy of this many bytes (profiler calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for "
+              f"--gpus {args.gpus}); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2510_09892_amd import inputs, sphint
+
+    sphint.load()
+    log(f"[bench] generating {args.n} ill-conditioned arcs")
+    P = inputs.ill_conditioned(args.n, seed_tag=1)
+    dev = [torch.from_numpy(a).cuda() for a in P.soa()]
+    torch.cuda.synchronize()
+
+    res = {}
+    for mode in args.modes.split(","):
+        log(f"[bench] mode={mode} warmup={args.warmup} steps={args.steps}")
+        res[mode] = run_mode(torch, sphint, dev, mode, args.steps, args.warmup)
+        r = res[mode]
+        log(f"[bench] mode={mode} wall={r['wall_s']:.4f}s kernel_mean={statistics.mean(r['kernel_ms']):.4f}ms "
+            f"hits={r['total']}")
+
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {args.copy_calibration} bytes x3")
+
+    n = args.n
+    head = "eft" if "eft" in res else next(iter(res))
+    r = res[head]
+    value = n * args.steps / r["wall_s"]
+    kms = statistics.mean(r["kernel_ms"])
+    hits = r["total"]
+    bytes_launch = BYTES_PER_PAIR * n + BYTES_PER_HIT * hits
+    if head == "eft":
+        ops_launch = EFT_OPS_PER_PAIR * n + EFT_OPS_PER_HIT * hits
+    else:
+        ops_launch = NAIVE_OPS_PER_PAIR * n
+    bw = bytes_launch / (kms * 1e-3)
+    ops = ops_launch / (kms * 1e-3)
+    hbm = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+           "frac": bw / HBM_PEAK}
+    alu = {"bound": "alu", "achieved": ops / 1e12, "peak": ALU_PEAK / 1e12,
+           "unit": "Tlane-op/s (binary64)", "frac": ops / ALU_PEAK}
+    roof = dict(hbm if hbm["frac"] >= alu["frac"] else alu)
+    other = alu if roof["bound"] == "hbm" else hbm
+    roof["traffic"] = None
+    roof["kernel"] = f"k_intersect<{1 if head == 'eft' else 0},1>"
+    roof["kernel_ms"] = kms
+    roof["algorithmic_bytes"] = bytes_launch
+    roof["algorithmic_ops"] = ops_launch
+    roof["other_bound"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "intersections/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["wall_s"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "1e7 ill-conditioned arcs in three parts (short 1e-10..1e-6 rad; "
+                               "near-tangent r<=1e-12; within 1e-6 rad of a pole), one latitude "
+                               "per arc, dense 1:1, mode " + head,
+                   "pairs": n, "hits": hits},
+        "roofline": roof,
+    }
+    if "naive" in res and head != "naive":
+        rn = res["naive"]
+        nv = n * args.steps / rn["wall_s"]
+        line["naive"] = {"value": nv, "ms_per_step": rn["wall_s"] / args.steps * 1e3,
+                         "kernel_ms": statistics.mean(rn["kernel_ms"]), "hits": rn["total"]}
+        line["eft_over_naive"] = value / nv
+    if not args.no_latency:
+        log("[bench] latency, 1e5 uniform arcs")
+        line["latency_1e5"] = latency_small(torch, sphint, inputs)
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_sample} pairs")
+        line["cpu_baseline"] = cpu_baseline(P, inputs, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

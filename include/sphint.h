@@ -1,0 +1,175 @@
+/*
+ * sphint: intersections of great-circle arcs with lines of constant latitude on MI355X.
+ *
+ * The operation (Chen, Ullrich & Panetta, "Fast and Accurate Intersections on a Sphere",
+ * Sec. 1.2 problem definition and Sec. 2): given binary64 arc endpoints x1, x2 (any
+ * nonzero length; the arc is the shorter great-circle path between x1/|x1| and x2/|x2|)
+ * and a latitude z = z0, return the 0, 1 or 2 points P = (P_x, P_y, z0) of the unit
+ * sphere where the arc meets the latitude circle.  Points follow Eq. (2.2):
+ *
+ *     P = -( z0 n_x n_z +- s n_y , z0 n_y n_z -+ s n_x ) / |n_xy|^2 ,
+ *     n = x1 x x2,  s = sqrt(|n_xy|^2 - |n|^2 z0^2),
+ *
+ * root SPHINT_ROOT_PLUS taking the upper signs (the crossing where z increases along the
+ * arc from x1 to x2) and SPHINT_ROOT_MINUS the lower signs.
+ *
+ * Modes:
+ *   SPHINT_NAIVE_FP64  Eq. (2.2) operation by operation in binary64 (Sec. 4), with binary64
+ *                      existence/containment tests that take the endpoint heights as the
+ *                      raw z1, z2 (inputs assumed unit length).
+ *   SPHINT_EFT_FP64    Alg. 8 (AccuX, Sec. 6) with error-free transformations (the normal's
+ *                      compensated pairs renormalised before the sums of squares); hit
+ *                      counts, roots and flags are exact (containment against the
+ *                      normalised endpoints x_i/|x_i|; exact ties count, i.e. the arc is
+ *                      closed); each point is within 4 * 2^-53 (max-norm) of the exact
+ *                      intersection away from tangency (s well above 2^-53 |n|).
+ *
+ * Inputs must be finite for a result (non-finite inputs give 0 hits and
+ * SPHINT_F_NONFINITE) and, for the exactness claims, nonzero magnitudes roughly within
+ * [2^-150, 2^150] (no overflow or underflow in products of up to six inputs).
+ *
+ * Memory: every array argument is DEVICE memory owned by the caller; the library never
+ * allocates on these calls.  Calls are asynchronous on `stream` (a hipStream_t; NULL is the
+ * default stream): outputs are valid once the stream reaches the end of the call.  All
+ * entry points are reentrant; concurrent calls must use distinct workspaces.
+ */
+#ifndef SPHINT_H
+#define SPHINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SPHINT_NAIVE_FP64 = 0, SPHINT_EFT_FP64 = 1 } sphint_mode;
+
+typedef enum {
+  SPHINT_OK = 0,
+  SPHINT_E_INVAL = 1,    /* invalid argument; nothing was launched */
+  SPHINT_E_CAPACITY = 2, /* reported by sphint_check: *out_total exceeded out.capacity */
+  SPHINT_E_HIP = 3,      /* a HIP runtime call failed */
+  SPHINT_E_NOMEM = 4,    /* host allocation failed (plans only) */
+  SPHINT_E_DEVICE = 5    /* the kernel reported an internal limit (see sphint_check) */
+} sphint_status;
+
+/* Per-pair flag bits (out_flags). */
+#define SPHINT_F_EXISTS 1u    /* the great circle meets the latitude circle: s^2 >= 0 */
+#define SPHINT_F_TANGENT 2u   /* s^2 == 0: the circles touch; a double root counted once */
+#define SPHINT_F_DEGEN_N 4u   /* n == 0: zero, equal or antipodal endpoints */
+#define SPHINT_F_HORIZ 8u     /* n_xy == 0, n != 0: the arc lies on the equator */
+#define SPHINT_F_NONFINITE 16u/* an input is inf or nan */
+
+#define SPHINT_ROOT_PLUS 0
+#define SPHINT_ROOT_MINUS 1
+
+/* Structure-of-arrays endpoints: component k of point i is x[i], y[i], z[i]. */
+typedef struct {
+  const double *x, *y, *z;
+} sphint_pts_soa;
+
+/* Compacted hit output.  Hit j is (x[j], y[j], z0 of pair[j]); root[j] is SPHINT_ROOT_*.
+ * Hits are ordered by pair index, and within a pair along the arc from x1 to x2.  Writes
+ * stop at `capacity` hits (2 * number of pairs always suffices); *out_total still holds the
+ * required count. */
+typedef struct {
+  double *x, *y;
+  int64_t *pair;
+  uint8_t *root;
+  int64_t capacity;
+} sphint_hits;
+
+/*
+ * Intersections for a batch of arc-latitude pairs.
+ *
+ * Pairs (Sec. 1.2 inputs x1, x2, z0):
+ *   dense form  (lat_offsets == NULL, lat_idx == NULL): pair i is arc i with latitude
+ *               lat_z[i]; n_lat must equal n_arcs and nnz must equal n_arcs.
+ *   CSR form    pair k is (arc i, latitude lat_z[lat_idx[k]]) for k in
+ *               [lat_offsets[i], lat_offsets[i+1]); lat_offsets has n_arcs + 1
+ *               non-decreasing entries with lat_offsets[0] == 0 and lat_offsets[n_arcs] ==
+ *               nnz; lat_idx has nnz entries in [0, n_lat).  An out-of-range lat_idx entry
+ *               yields a NONFINITE pair, not a memory access out of bounds.
+ * p1, p2      arc endpoints, n_arcs entries per component (device).
+ * out         compacted hits (device); may have capacity 0 with NULL pointers.
+ * out_count   [nnz] hit count per pair, 0..2 (device, required when nnz > 0).
+ * out_flags   [nnz] SPHINT_F_* per pair (device, may be NULL).
+ * out_total   one int64 (device): total hits of this call.
+ * workspace   device memory of at least sphint_workspace_size(nnz) bytes, 256-byte
+ *             aligned, used only by this call while it runs.
+ * Returns SPHINT_E_INVAL (no launch) for negative sizes, missing pointers, mismatched
+ * dense sizes or a short workspace; SPHINT_E_HIP if a launch fails; else SPHINT_OK.
+ */
+sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1, sphint_pts_soa p2,
+                                  const double *lat_z, int64_t n_lat,
+                                  const int64_t *lat_offsets, const int32_t *lat_idx,
+                                  int64_t nnz, sphint_hits out, uint8_t *out_count,
+                                  uint8_t *out_flags, int64_t *out_total, sphint_mode mode,
+                                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes sphint_arc_constlat needs for `nnz` pairs (any mode or form). */
+size_t sphint_workspace_size(int64_t nnz);
+
+/*
+ * After the stream has completed a call that used `workspace`: SPHINT_E_DEVICE if a kernel
+ * hit an internal limit (bounded wait or exact-arithmetic capacity), SPHINT_E_CAPACITY if
+ * host_total (the value of *out_total copied back by the caller) exceeds capacity, else
+ * SPHINT_OK.  Synchronous (reads 8 bytes of the workspace).
+ */
+sphint_status sphint_check(const void *workspace, int64_t host_total, int64_t capacity);
+
+/*
+ * Instrumentation.  While set (non-NULL), every sphint_arc_constlat call made from this host
+ * thread records `start` (a hipEvent_t) on its stream immediately before its main kernel and
+ * `stop` immediately after it, so the caller can time that kernel alone; NULL, NULL stops
+ * it.  The events are owned by the caller.
+ */
+sphint_status sphint_set_profile_events(void *start, void *stop);
+
+/* ------------------------------------------------------------------ batched meshes */
+
+/* One independent mesh of a batch: the arguments of one CSR (or dense) call. */
+typedef struct {
+  int64_t n_arcs, n_lat, nnz;
+  sphint_pts_soa p1, p2;
+  const double *lat_z;
+  const int64_t *lat_offsets; /* NULL for the dense form */
+  const int32_t *lat_idx;
+  sphint_hits out;
+  uint8_t *out_count, *out_flags;
+  int64_t *out_total;
+} sphint_mesh_desc;
+
+typedef struct sphint_plan sphint_plan;
+
+/*
+ * Plan for running many meshes in one persistent launch.  Copies the descriptors to the
+ * device (the one allocation of the plan, owned by it) and prepares the tile schedule.
+ * Each mesh's results equal a sphint_arc_constlat call on that mesh alone.
+ */
+sphint_status sphint_batch_plan_create(const sphint_mesh_desc *meshes, int n_meshes,
+                                       sphint_mode mode, sphint_plan **plan);
+/* Times the plan's candidate schedules (pairs per thread 1, 2, 4 x persistent grid sizes)
+ * by running the whole batch on `stream`, keeps the fastest, and synchronizes the stream;
+ * reads/appends a text cache at cache_path (may be NULL) keyed by the plan's shape.  The
+ * batch's outputs are overwritten (with the same values). */
+sphint_status sphint_batch_autotune(sphint_plan *plan, const char *cache_path, void *stream);
+/* Launches the plan on `stream`: the first launch captures the init and persistent kernels
+ * into a HIP graph (on a stream of the plan's own), every launch replays it. */
+sphint_status sphint_batch_launch(sphint_plan *plan, void *stream);
+/* Schedule of the plan: pairs per thread (tile = 256 * pairs_per_thread pairs) and resident
+ * workgroups per compute unit of the persistent grid (0: one workgroup per tile). */
+sphint_status sphint_batch_params(const sphint_plan *plan, int *pairs_per_thread,
+                                  int *wg_per_cu);
+void sphint_plan_destroy(sphint_plan *plan);
+
+const char *sphint_status_string(sphint_status s);
+/* "sphint <version> gfx950" */
+const char *sphint_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPHINT_H */

@@ -43,6 +43,9 @@ def _naive_chunk(rows):
 def _eft_chunk(jobs):
     out = []
     for (a, b, c, d, e, f, z, roots) in jobs:
+        if not roots:
+            out.append([])
+            continue
         q = eft.accux_parts((a, b, c), (d, e, f), z)
         pts = []
         for r in roots:

@@ -1,0 +1,112 @@
+// C-ABI entry points of libsphint (declared in include/sphint.h).
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <string.h>
+
+#include "sphint.h"
+#include "sphint_host.hpp"
+
+using namespace sphint;
+
+namespace {
+
+// Clears the tile states, counter and error word; writes *ototal = 0 for empty calls.
+__global__ void k_init(uint32_t* ws, uint64_t* status, int64_t ntiles, int64_t* ototal,
+                       int64_t nnz) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    ws[0] = 0u;
+    ws[1] = 0u;
+    if (nnz == 0) *ototal = 0;
+  }
+  for (int64_t k = t; k < ntiles; k += (int64_t)gridDim.x * blockDim.x) status[k] = 0ull;
+}
+
+constexpr int PPT_SINGLE = 1;  // pairs per thread of single calls
+
+thread_local hipEvent_t prof_start = nullptr, prof_stop = nullptr;
+
+template <int MODE>
+hipError_t launch_main(const KArgs& k, hipStream_t st) {
+  hipLaunchKernelGGL((k_intersect<MODE, PPT_SINGLE>), dim3((unsigned)k.ntiles), dim3(BLOCK), 0,
+                     st, k);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" size_t sphint_workspace_size(int64_t nnz) {
+  int64_t t = tiles_for(nnz < 0 ? 0 : nnz);
+  return WS_HEADER + 8 * (size_t)(t > 0 ? t : 1);
+}
+
+extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
+                                             sphint_pts_soa p2, const double* lat_z,
+                                             int64_t n_lat, const int64_t* lat_offsets,
+                                             const int32_t* lat_idx, int64_t nnz,
+                                             sphint_hits out, uint8_t* out_count,
+                                             uint8_t* out_flags, int64_t* out_total,
+                                             sphint_mode mode, void* workspace,
+                                             size_t workspace_bytes, void* stream) {
+  if (mode != SPHINT_NAIVE_FP64 && mode != SPHINT_EFT_FP64) return SPHINT_E_INVAL;
+  sphint_status v = validate(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out,
+                             out_count, out_total);
+  if (v != SPHINT_OK) return v;
+  if (!workspace || !aligned256(workspace) || workspace_bytes < sphint_workspace_size(nnz))
+    return SPHINT_E_INVAL;
+  const int64_t ntiles = tiles_for(nnz);
+  if (ntiles > 0x7fffffffLL) return SPHINT_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* ws = (uint32_t*)workspace;
+  uint64_t* status = (uint64_t*)((char*)workspace + WS_HEADER);
+
+  int64_t init_threads = ntiles > 0 ? ntiles : 1;
+  unsigned init_blocks = (unsigned)((init_threads + 255) / 256);
+  if (init_blocks > 1024) init_blocks = 1024;
+  hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, ws, status, ntiles, out_total,
+                     nnz);
+  if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
+  if (nnz == 0) return SPHINT_OK;
+
+  KArgs k = make_args(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out, out_count,
+                      out_flags, out_total, ws, status, ntiles);
+  if (prof_start && hipEventRecord(prof_start, st) != hipSuccess) return SPHINT_E_HIP;
+  hipError_t e = mode == SPHINT_EFT_FP64 ? launch_main<1>(k, st) : launch_main<0>(k, st);
+  if (e == hipSuccess && prof_stop) e = hipEventRecord(prof_stop, st);
+  return e == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
+}
+
+extern "C" sphint_status sphint_set_profile_events(void* start, void* stop) {
+  if ((start == nullptr) != (stop == nullptr)) return SPHINT_E_INVAL;
+  prof_start = (hipEvent_t)start;
+  prof_stop = (hipEvent_t)stop;
+  return SPHINT_OK;
+}
+
+extern "C" sphint_status sphint_check(const void* workspace, int64_t host_total,
+                                      int64_t capacity) {
+  if (!workspace) return SPHINT_E_INVAL;
+  uint32_t hdr[2] = {0, 0};
+  if (hipMemcpy(hdr, workspace, sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess)
+    return SPHINT_E_HIP;
+  if (hdr[1]) return SPHINT_E_DEVICE;
+  if (host_total > capacity) return SPHINT_E_CAPACITY;
+  return SPHINT_OK;
+}
+
+extern "C" const char* sphint_status_string(sphint_status s) {
+  switch (s) {
+    case SPHINT_OK: return "ok";
+    case SPHINT_E_INVAL: return "invalid argument";
+    case SPHINT_E_CAPACITY: return "hit output capacity exceeded";
+    case SPHINT_E_HIP: return "HIP runtime error";
+    case SPHINT_E_NOMEM: return "out of memory";
+    case SPHINT_E_DEVICE: return "kernel reported an internal limit";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* sphint_version(void) { return "sphint 0.1 gfx950"; }

@@ -1,0 +1,341 @@
+// Batched meshes: many independent CSR (or dense) calls in one persistent launch.
+//
+// The tiles of all meshes form one sequence (mesh 0's tiles, then mesh 1's, ...).  A
+// persistent grid of workgroups takes tiles from one atomic counter; each tile belongs to one
+// mesh and runs exactly the single-call tile routine on that mesh's arguments, with the
+// mesh's own slice of look-back states, so every mesh's outputs equal those of a
+// sphint_arc_constlat call on that mesh alone.  Tiles of one mesh are taken in increasing
+// order, which keeps the look-back's waits on tiles that are already running.
+//
+// Schedule parameters: pairs per thread (tile = 256 * ppt pairs) and the number of resident
+// workgroups per CU; sphint_batch_autotune times the candidates and keeps the fastest.  The
+// init kernel and the persistent kernel are captured once into a HIP graph and replayed.
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sphint_host.hpp"
+
+using namespace sphint;
+
+template <int MODE, int PPT>
+__global__ __launch_bounds__(BLOCK) void k_batch(const KArgs* __restrict__ args,
+                                                 const int64_t* __restrict__ tile_base,
+                                                 int n_meshes, int64_t total_tiles,
+                                                 uint32_t* counter) {
+  __shared__ TileShared<MODE, PPT> sh;
+  __shared__ int64_t s_tile;
+  __shared__ int s_mesh;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int64_t t = (int64_t)atomicAdd(counter, 1u);
+      int lo = 0, hi = n_meshes - 1;
+      while (lo < hi) {  // largest mesh whose first tile is <= t
+        int mid = (lo + hi + 1) >> 1;
+        if (tile_base[mid] <= t) lo = mid;
+        else hi = mid - 1;
+      }
+      s_tile = t;
+      s_mesh = lo;
+    }
+    __syncthreads();
+    const int64_t t = s_tile;
+    if (t >= total_tiles) break;  // every workgroup leaves once the tiles run out
+    const int m = s_mesh;
+    const KArgs a = args[m];
+    run_tile<MODE, PPT>(a, t - tile_base[m], sh);
+    __syncthreads();
+  }
+}
+
+__global__ void k_batch_init(uint32_t* ws, uint64_t* status, int64_t total_tiles,
+                             const KArgs* __restrict__ args, int n_meshes) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    ws[0] = 0u;
+    ws[1] = 0u;
+  }
+  if (t < n_meshes && args[t].nnz == 0) *args[t].ototal = 0;
+  for (int64_t k = t; k < total_tiles; k += (int64_t)gridDim.x * blockDim.x) status[k] = 0ull;
+}
+
+struct sphint_plan {
+  sphint_mode mode = SPHINT_EFT_FP64;
+  std::vector<sphint_mesh_desc> meshes;
+  int device = 0;
+  int cus = 1;
+  // schedule
+  int ppt = 1;
+  int wg_per_cu = 0;  // 0: one workgroup per tile (non-persistent grid)
+  // device state
+  KArgs* d_args = nullptr;
+  int64_t* d_tile_base = nullptr;
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<int64_t> tile_base;
+  int64_t total_tiles = 0;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+template <int MODE, int PPT>
+int max_resident() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MODE, PPT>, BLOCK, 0) !=
+      hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
+}
+
+int resident_per_cu(sphint_mode mode, int ppt) {
+  if (mode == SPHINT_EFT_FP64) {
+    if (ppt == 1) return max_resident<1, 1>();
+    if (ppt == 2) return max_resident<1, 2>();
+    return max_resident<1, 4>();
+  }
+  if (ppt == 1) return max_resident<0, 1>();
+  if (ppt == 2) return max_resident<0, 2>();
+  return max_resident<0, 4>();
+}
+
+void drop_graph(sphint_plan* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  p->exec = nullptr;
+}
+
+// (Re)lays out tiles for the plan's ppt and uploads the per-mesh arguments.
+sphint_status layout(sphint_plan* p) {
+  drop_graph(p);
+  const int n = (int)p->meshes.size();
+  p->tile_base.assign(n + 1, 0);
+  for (int m = 0; m < n; ++m)
+    p->tile_base[m + 1] = p->tile_base[m] + tiles_for(p->meshes[m].nnz, p->ppt);
+  p->total_tiles = p->tile_base[n];
+  if (p->total_tiles > 0x7fffffffLL) return SPHINT_E_INVAL;
+  const size_t need = WS_HEADER + 8 * (size_t)(p->total_tiles > 0 ? p->total_tiles : 1);
+  if (need > p->ws_bytes) {
+    if (p->d_ws) (void)hipFree(p->d_ws);
+    p->d_ws = nullptr;
+    if (hipMalloc(&p->d_ws, need) != hipSuccess) return SPHINT_E_HIP;
+    p->ws_bytes = need;
+  }
+  uint32_t* ws = (uint32_t*)p->d_ws;
+  uint64_t* status = (uint64_t*)((char*)p->d_ws + WS_HEADER);
+  std::vector<KArgs> h(n);
+  for (int m = 0; m < n; ++m) {
+    const sphint_mesh_desc& d = p->meshes[m];
+    h[m] = make_args(d.n_arcs, d.p1, d.p2, d.lat_z, d.n_lat, d.lat_offsets, d.lat_idx, d.nnz,
+                     d.out, d.out_count, d.out_flags, d.out_total, ws,
+                     status + p->tile_base[m], p->tile_base[m + 1] - p->tile_base[m]);
+  }
+  if (hipMemcpy(p->d_args, h.data(), sizeof(KArgs) * n, hipMemcpyHostToDevice) != hipSuccess)
+    return SPHINT_E_HIP;
+  if (hipMemcpy(p->d_tile_base, p->tile_base.data(), sizeof(int64_t) * (n + 1),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return SPHINT_E_HIP;
+  return SPHINT_OK;
+}
+
+template <int MODE, int PPT>
+void launch_batch(const sphint_plan* p, unsigned grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_batch<MODE, PPT>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
+                     p->d_tile_base, (int)p->meshes.size(), p->total_tiles, (uint32_t*)p->d_ws);
+}
+
+// Enqueues init + persistent kernel on st (no graph).
+sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
+  uint32_t* ws = (uint32_t*)p->d_ws;
+  uint64_t* status = (uint64_t*)((char*)p->d_ws + WS_HEADER);
+  const int n = (int)p->meshes.size();
+  int64_t work = p->total_tiles > n ? p->total_tiles : n;
+  unsigned ib = (unsigned)((work + 255) / 256);
+  if (ib > 1024) ib = 1024;
+  if (ib == 0) ib = 1;
+  hipLaunchKernelGGL(k_batch_init, dim3(ib), dim3(256), 0, st, ws, status, p->total_tiles,
+                     p->d_args, n);
+  if (p->total_tiles > 0) {
+    int64_t grid = p->total_tiles;
+    if (p->wg_per_cu > 0) {
+      int64_t res = (int64_t)p->wg_per_cu * p->cus;
+      if (res < grid) grid = res;
+    }
+    const bool eft = p->mode == SPHINT_EFT_FP64;
+    if (p->ppt == 1) eft ? launch_batch<1, 1>(p, (unsigned)grid, st) : launch_batch<0, 1>(p, (unsigned)grid, st);
+    else if (p->ppt == 2) eft ? launch_batch<1, 2>(p, (unsigned)grid, st) : launch_batch<0, 2>(p, (unsigned)grid, st);
+    else eft ? launch_batch<1, 4>(p, (unsigned)grid, st) : launch_batch<0, 4>(p, (unsigned)grid, st);
+  }
+  return hipGetLastError() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
+}
+
+std::string plan_key(const sphint_plan* p) {
+  int64_t nnz = 0, arcs = 0;
+  for (const auto& m : p->meshes) {
+    nnz += m.nnz;
+    arcs += m.n_arcs;
+  }
+  char buf[160];
+  snprintf(buf, sizeof(buf), "mode=%d meshes=%zu arcs=%lld nnz=%lld cus=%d", (int)p->mode,
+           p->meshes.size(), (long long)arcs, (long long)nnz, p->cus);
+  return buf;
+}
+
+}  // namespace
+
+extern "C" sphint_status sphint_batch_plan_create(const sphint_mesh_desc* meshes, int n_meshes,
+                                                  sphint_mode mode, sphint_plan** plan) {
+  if (!plan || n_meshes <= 0 || !meshes) return SPHINT_E_INVAL;
+  if (mode != SPHINT_NAIVE_FP64 && mode != SPHINT_EFT_FP64) return SPHINT_E_INVAL;
+  *plan = nullptr;
+  for (int m = 0; m < n_meshes; ++m) {
+    const sphint_mesh_desc& d = meshes[m];
+    sphint_status v = validate(d.n_arcs, d.p1, d.p2, d.lat_z, d.n_lat, d.lat_offsets,
+                               d.lat_idx, d.nnz, d.out, d.out_count, d.out_total);
+    if (v != SPHINT_OK) return v;
+  }
+  sphint_plan* p = new (std::nothrow) sphint_plan();
+  if (!p) return SPHINT_E_NOMEM;
+  p->mode = mode;
+  p->meshes.assign(meshes, meshes + n_meshes);
+  (void)hipGetDevice(&p->device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) p->cus = prop.multiProcessorCount;
+  if (hipMalloc((void**)&p->d_args, sizeof(KArgs) * n_meshes) != hipSuccess ||
+      hipMalloc((void**)&p->d_tile_base, sizeof(int64_t) * (n_meshes + 1)) != hipSuccess) {
+    sphint_plan_destroy(p);
+    return SPHINT_E_HIP;
+  }
+  p->ppt = 1;
+  p->wg_per_cu = resident_per_cu(mode, 1);
+  sphint_status s = layout(p);
+  if (s != SPHINT_OK) {
+    sphint_plan_destroy(p);
+    return s;
+  }
+  *plan = p;
+  return SPHINT_OK;
+}
+
+extern "C" sphint_status sphint_batch_launch(sphint_plan* p, void* stream) {
+  if (!p) return SPHINT_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (!p->exec) {
+    if (!p->capture_stream &&
+        hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
+      return SPHINT_E_HIP;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return SPHINT_E_HIP;
+    sphint_status s = enqueue(p, p->capture_stream);
+    hipError_t e = hipStreamEndCapture(p->capture_stream, &g);
+    if (s != SPHINT_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return SPHINT_E_HIP;
+    }
+    e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      p->exec = nullptr;
+      return SPHINT_E_HIP;
+    }
+  }
+  return hipGraphLaunch(p->exec, st) == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
+}
+
+extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache_path,
+                                               void* stream) {
+  if (!p) return SPHINT_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const std::string key = plan_key(p);
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[512];
+      while (fgets(line, sizeof(line), f)) {
+        char* bar = strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        if (key == line) {
+          int ppt = 0, wg = -1;
+          if (sscanf(bar + 1, "%d %d", &ppt, &wg) == 2 && (ppt == 1 || ppt == 2 || ppt == 4) &&
+              wg >= 0) {
+            fclose(f);
+            p->ppt = ppt;
+            p->wg_per_cu = wg;
+            return layout(p);
+          }
+        }
+      }
+      fclose(f);
+    }
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SPHINT_E_HIP;
+  float best = 1e30f;
+  int best_ppt = 1, best_wg = 0;
+  const int ppts[3] = {1, 2, 4};
+  for (int pi = 0; pi < 3; ++pi) {
+    const int ppt = ppts[pi];
+    const int res = resident_per_cu(p->mode, ppt);
+    const int wgs[4] = {0, res, res > 1 ? res / 2 : 1, 2 * res};
+    for (int wi = 0; wi < 4; ++wi) {
+      p->ppt = ppt;
+      p->wg_per_cu = wgs[wi];
+      sphint_status s = layout(p);
+      if (s != SPHINT_OK) return s;
+      if (enqueue(p, st) != SPHINT_OK) return SPHINT_E_HIP;  // warm-up
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < 3; ++r)
+        if (enqueue(p, st) != SPHINT_OK) return SPHINT_E_HIP;
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) return SPHINT_E_HIP;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_ppt = ppt;
+        best_wg = wgs[wi];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->ppt = best_ppt;
+  p->wg_per_cu = best_wg;
+  sphint_status s = layout(p);
+  if (s == SPHINT_OK && cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%s|%d %d\n", key.c_str(), best_ppt, best_wg);
+      fclose(f);
+    }
+  }
+  return s;
+}
+
+extern "C" sphint_status sphint_batch_params(const sphint_plan* p, int* pairs_per_thread,
+                                             int* wg_per_cu) {
+  if (!p) return SPHINT_E_INVAL;
+  if (pairs_per_thread) *pairs_per_thread = p->ppt;
+  if (wg_per_cu) *wg_per_cu = p->wg_per_cu;
+  return SPHINT_OK;
+}
+
+extern "C" void sphint_plan_destroy(sphint_plan* p) {
+  if (!p) return;
+  drop_graph(p);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  if (p->d_args) (void)hipFree(p->d_args);
+  if (p->d_tile_base) (void)hipFree(p->d_tile_base);
+  if (p->d_ws) (void)hipFree(p->d_ws);
+  delete p;
+}

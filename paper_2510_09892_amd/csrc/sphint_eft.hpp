@@ -1,0 +1,124 @@
+// Error-free transformations and the AccuX building blocks for gfx950 (binary64 VALU).
+//
+// Chen, Ullrich & Panetta, "Fast and Accurate Intersections on a Sphere": Sec. 5 (accurate
+// operators, Alg. 1-7) and Sec. 6 (AccuX, Alg. 8).  Every operation below is one IEEE
+// binary64 rounding (round to nearest even); FMAs appear only where an algorithm asks for
+// one.  Contraction is off for this whole translation unit: a compiler-fused a*b+c would
+// change the rounding the error-free transformations rely on (the paper builds with
+// -ffp-contract=off for the same reason, Sec. 7.2).
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sphint {
+
+struct dd {
+  double hi, lo;
+};
+
+// Knuth TwoSum: s = fl(a+b), e = a + b - s exactly; no precondition (6 operations).
+__host__ __device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b;
+  double bv = s - a;
+  double av = s - bv;
+  return {s, (a - av) + (b - bv)};
+}
+
+// Dekker FastTwoSum: exact when exponent(a) >= exponent(b) (3 operations).
+__host__ __device__ __forceinline__ dd fast_two_sum(double a, double b) {
+  double s = a + b;
+  return {s, b - (s - a)};
+}
+
+// TwoProduct with a single-rounding FMA: a*b = p + e exactly.
+__host__ __device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, __builtin_fma(a, b, -p)};
+}
+
+__host__ __device__ __forceinline__ int sgn(double v) { return (v > 0.0) - (v < 0.0); }
+
+// Alg. 4 (AccuDOP), read as a*b - c*d with compensation fl(s + fl(r1 - r2)) (the exact
+// identity a*b - c*d = (p1 - p2) + (r1 - r2)), followed by a TwoSum renormalisation so that
+// |lo| <= u |hi|; mag = |p1| + |p2| bounds the compensation error (3.01 u^2 mag).
+struct dop3 {
+  double hi, lo, mag;
+};
+__host__ __device__ __forceinline__ dop3 accu_dop(double a, double b, double c, double d) {
+  dd p1 = two_prod(a, b);
+  dd p2 = two_prod(c, d);
+  dd t = two_sum(p1.hi, -p2.hi);
+  double err = t.lo + (p1.lo - p2.lo);
+  dd n = two_sum(t.hi, err);
+  return {n.hi, n.lo, __builtin_fabs(p1.hi) + __builtin_fabs(p2.hi)};
+}
+
+// Alg. 6 (SumNonNeg).
+__host__ __device__ __forceinline__ dd sum_non_neg(dd A, dd B) {
+  dd H = two_sum(A.hi, B.hi);
+  double c = A.lo + B.lo;
+  double d = H.lo + c;
+  return fast_two_sum(H.hi, d);
+}
+
+// Quantities of one arc that every latitude of that arc shares (Alg. 8 lines 2-6, 13-16
+// and 18-21), plus what the exact hit test needs.
+struct ArcEft {
+  double nx, enx, ny, eny, nz, enz;  // normal n = x1 x x2 as renormalised pairs
+  double mx, my, mz;                 // AccuDOP magnitudes
+  double S2, s2, S3, s3;             // |n_xy|^2 and |n|^2 as pairs (Alg. 7)
+  double Fx, eFx, Fy, eFy;           // n_x n_z and n_y n_z as pairs
+  double nrm1, nrm2;                 // binary64 |x1|, |x2| (filters only)
+  double z1, z2;
+  int d1, d2;                        // exact signs of dz/dt at the endpoints
+  unsigned flags;
+};
+
+// Alg. 7 (SumOfSquaresC) for the 2-D and 3-D normal at once: the 3-D sums continue the
+// 2-D ones term by term, exactly as running Alg. 5 and Alg. 1 over three terms does.
+__host__ __device__ __forceinline__ void norms(ArcEft& a) {
+  dd st = two_prod(a.nx, a.nx);               // SumNonNeg([0,0], [P,p]) == [P,p]
+  st = sum_non_neg(st, two_prod(a.ny, a.ny));  // SumOfSquares over (n_x, n_y)
+  dd cp = two_prod(a.nx, a.enx);               // CompDotC over (n_x, n_y).(e_x, e_y)
+  dd h = two_prod(a.ny, a.eny);
+  dd q = two_sum(cp.hi, h.hi);
+  double cs = cp.lo + (q.lo + h.lo);
+  double cph = q.hi;
+  double R2s = cph + cs;                        // CompDot
+  double R2 = __builtin_fma(2.0, R2s, st.lo);
+  dd S2 = fast_two_sum(st.hi, R2);
+  a.S2 = S2.hi;
+  a.s2 = S2.lo;
+  dd st3 = sum_non_neg(st, two_prod(a.nz, a.nz));
+  dd h3 = two_prod(a.nz, a.enz);
+  dd q3 = two_sum(cph, h3.hi);
+  double cs3 = cs + (q3.lo + h3.lo);
+  double R3s = q3.hi + cs3;
+  double R3 = __builtin_fma(2.0, R3s, st3.lo);
+  dd S3 = fast_two_sum(st3.hi, R3);
+  a.S3 = S3.hi;
+  a.s3 = S3.lo;
+}
+
+// Alg. 8 lines 13-16 / 18-21: (F, e_F) = n_a n_z as a pair.
+__host__ __device__ __forceinline__ dd f_pair(double na, double ena, double nz, double enz) {
+  dd f = two_prod(na, nz);
+  double e2 = na * enz;
+  double e3 = nz * ena;
+  return {f.hi, (f.lo + e2) + e3};
+}
+
+// AccSqrt of the pair (a, e), |e| <= u a: double-word square root with one first-order
+// correction and a FastTwoSum renormalisation (relative error 25/8 u^2).
+__host__ __device__ __forceinline__ dd acc_sqrt(double a, double e) {
+  if (!(a > 0.0)) return {0.0, 0.0};
+  double sh = __builtin_sqrt(a);
+  double rho1 = __builtin_fma(-sh, sh, a);
+  double rho2 = rho1 + e;
+  double sl = rho2 / (2.0 * sh);
+  return fast_two_sum(sh, sl);
+}
+
+}  // namespace sphint

@@ -1,0 +1,41 @@
+// CPU build of the per-pair arithmetic, for tests only (never a product path: the library's
+// entry points run on the GPU and nothing in the package loads this object).  It compiles
+// the same header the kernels use, so the CPU tests exercise the exact operation sequence
+// of the GPU evaluation; undecided predicates are resolved immediately instead of one lane
+// at a time.
+#include "sphint_pair.hpp"
+
+extern "C" int sphint_hostcheck_eval(int mode, int64_t n, const double* x1, const double* y1,
+                                     const double* z1, const double* x2, const double* y2,
+                                     const double* z2, const double* z0, int32_t* count,
+                                     int32_t* flags, int32_t* r0, int32_t* r1, double* px0,
+                                     double* py0, double* px1, double* py1) {
+  using namespace sphint;
+  static thread_local double arena[xp::ARENA];
+  for (int64_t i = 0; i < n; ++i) {
+    PairOut o;
+    if (mode == 1)
+      o = eval_eft(true, x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], z0[i], arena,
+                   [](bool need, auto&& fn) {
+                     if (need) fn();
+                   });
+    else
+      o = eval_naive(true, x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], z0[i]);
+    count[i] = o.count;
+    flags[i] = (int32_t)o.flags;
+    r0[i] = o.r0;
+    r1[i] = o.r1;
+    px0[i] = o.px0;
+    py0[i] = o.py0;
+    px1[i] = o.px1;
+    py1[i] = o.py1;
+  }
+  return 0;
+}
+
+// Exact sign of one predicate (sphint::PRED_*), for tests of the expansion arithmetic.
+extern "C" int sphint_hostcheck_exact_sign(int which, double x1, double y1, double z1, double x2,
+                                           double y2, double z2, double z0) {
+  static thread_local double arena[sphint::xp::ARENA];
+  return sphint::exact_sign(which, x1, y1, z1, x2, y2, z2, z0, arena);
+}

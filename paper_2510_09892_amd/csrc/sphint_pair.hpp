@@ -1,0 +1,445 @@
+// Per-arc and per-pair evaluation of the arc x constant-latitude intersection.
+//
+// Problem and formula: Sec. 1.2 and Sec. 2 of Chen, Ullrich & Panetta.  Two modes:
+//   * naive:  Eq. (2.2) translated operation by operation into binary64 (Sec. 4), with
+//             binary64 existence/containment tests and raw endpoint heights;
+//   * EFT:    Alg. 8 (AccuX) with the AccuDOP pairs renormalised, and exact existence and
+//             containment decisions (filters, then expansion arithmetic).
+//
+// Containment (Sec. 2 leaves the method open): along the minor arc, z is monotone or has
+// one interior extremum; with d_i = sign(dz/dt) at the endpoints (d_i = sign(n_x y_i -
+// n_y x_i)) and c_i = sign(z0 - z_i/|x_i|):
+//     d1 >= 0, d2 >= 0 : PLUS  iff c1 >= 0 && c2 <= 0
+//     d1 <= 0, d2 <= 0 : MINUS iff c2 >= 0 && c1 <= 0
+//     d1 > 0 > d2      : PLUS iff c1 >= 0, then MINUS iff c2 >= 0   (apex inside)
+//     d1 < 0 < d2      : MINUS iff c1 <= 0, then PLUS iff c2 <= 0   (nadir inside)
+// provided s^2 >= 0; at s^2 == 0 only the first listed hit is kept.  PLUS is Eq. (2.2) with
+// the upper signs (the ascending crossing), MINUS the lower signs.
+//
+// Everything here is __host__ __device__ so the identical arithmetic can be compiled for
+// the CPU in tests.  Decisions a filter cannot certify come back as UNDECIDED; the caller
+// resolves them with exact_sign (on the GPU, one lane at a time per wavefront).
+#pragma once
+#pragma clang fp contract(off)
+
+#include "sphint_eft.hpp"
+#include "sphint_exact.hpp"
+
+namespace sphint {
+
+enum : unsigned {
+  F_EXISTS = 1u,
+  F_TANGENT = 2u,
+  F_DEGEN_N = 4u,
+  F_HORIZ = 8u,
+  F_NONFINITE = 16u,
+  F_FALLBACK = 32u,  // diagnostic: an exact expansion evaluation decided this pair
+  F_INTERNAL = 64u,  // an exact evaluation exceeded its arena (outside the input domain)
+};
+enum : int { ROOT_PLUS = 0, ROOT_MINUS = 1 };
+constexpr int UNDECIDED = 2;
+
+__host__ __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// The containment rule above; returns the hit count, roots in along-arc order.
+__host__ __device__ __forceinline__ int hit_rule(int d1, int d2, int c1, int c2, bool tangent,
+                                                 int& r0, int& r1) {
+  int n = 0;
+  r0 = ROOT_PLUS;
+  r1 = ROOT_MINUS;
+  if (d1 >= 0 && d2 >= 0) {
+    n = (c1 >= 0 && c2 <= 0);
+    r0 = ROOT_PLUS;
+  } else if (d1 <= 0 && d2 <= 0) {
+    n = (c2 >= 0 && c1 <= 0);
+    r0 = ROOT_MINUS;
+  } else if (d1 > 0) {
+    bool a = c1 >= 0, b = c2 >= 0;
+    n = (int)a + (int)b;
+    r0 = a ? ROOT_PLUS : ROOT_MINUS;
+    r1 = ROOT_MINUS;
+  } else {
+    bool a = c1 <= 0, b = c2 <= 0;
+    n = (int)a + (int)b;
+    r0 = a ? ROOT_MINUS : ROOT_PLUS;
+    r1 = ROOT_PLUS;
+  }
+  if (tangent && n > 1) n = 1;
+  return n;
+}
+
+// Result of one pair: up to two points in along-arc order.
+struct PairOut {
+  double px0, py0, px1, py1;
+  int count, r0, r1;
+  unsigned flags;
+};
+
+// =========================================================================== naive mode
+
+struct ArcNaive {
+  double nx, ny, nz, S2, S3;
+  double x1, y1, z1, x2, y2, z2;
+  int d1, d2;
+  unsigned flags;
+};
+
+__host__ __device__ __forceinline__ void arc_naive(double x1, double y1, double z1, double x2,
+                                                   double y2, double z2, ArcNaive& a) {
+  a.x1 = x1; a.y1 = y1; a.z1 = z1; a.x2 = x2; a.y2 = y2; a.z2 = z2;
+  a.flags = 0;
+  a.d1 = a.d2 = 0;
+  a.nx = a.ny = a.nz = a.S2 = a.S3 = 0.0;
+  if (!(finite(x1) && finite(y1) && finite(z1) && finite(x2) && finite(y2) && finite(z2))) {
+    a.flags = F_NONFINITE;
+    return;
+  }
+  a.nx = y1 * z2 - z1 * y2;
+  a.ny = z1 * x2 - x1 * z2;
+  a.nz = x1 * y2 - y1 * x2;
+  if (a.nx == 0.0 && a.ny == 0.0 && a.nz == 0.0) {
+    a.flags = F_DEGEN_N;
+    return;
+  }
+  a.S2 = a.nx * a.nx + a.ny * a.ny;
+  if (a.S2 == 0.0) {
+    a.flags = F_HORIZ;
+    return;
+  }
+  a.S3 = a.S2 + a.nz * a.nz;
+  a.d1 = sgn(a.nx * y1 - a.ny * x1);
+  a.d2 = sgn(a.nx * y2 - a.ny * x2);
+}
+
+__host__ __device__ __forceinline__ PairOut pair_naive(const ArcNaive& a, double z0) {
+  PairOut o;
+  o.count = 0;
+  o.r0 = o.r1 = 0;
+  o.px0 = o.py0 = o.px1 = o.py1 = 0.0;
+  o.flags = a.flags;
+  if (a.flags) return o;
+  if (!finite(z0)) {
+    o.flags = F_NONFINITE;
+    return o;
+  }
+  double s2 = a.S2 - a.S3 * (z0 * z0);
+  if (s2 < 0.0) return o;
+  bool tangent = s2 == 0.0;
+  o.flags = F_EXISTS | (tangent ? F_TANGENT : 0u);
+  int c1 = sgn(z0 - a.z1);
+  int c2 = sgn(z0 - a.z2);
+  o.count = hit_rule(a.d1, a.d2, c1, c2, tangent, o.r0, o.r1);
+  if (o.count == 0) return o;
+  double s = __builtin_sqrt(s2);
+  double ax = (a.nx * a.nz) * z0;
+  double bx = s * a.ny;
+  double ay = (a.ny * a.nz) * z0;
+  double by = s * a.nx;
+  double xp = -((ax + bx) / a.S2), yp = -((ay - by) / a.S2);  // upper signs
+  double xm = -((ax - bx) / a.S2), ym = -((ay + by) / a.S2);  // lower signs
+  o.px0 = o.r0 == ROOT_PLUS ? xp : xm;
+  o.py0 = o.r0 == ROOT_PLUS ? yp : ym;
+  o.px1 = o.r1 == ROOT_PLUS ? xp : xm;
+  o.py1 = o.r1 == ROOT_PLUS ? yp : ym;
+  return o;
+}
+
+// =========================================================================== EFT mode
+
+// Sign of dz/dt at endpoint (x, y): n_x y - n_y x, filtered in two stages.
+// Stage 1 (binary64): error <= 3.01 u (|n_x y| + |n_y x|) + 3.01 u^2 (|y| m_x + |x| m_y).
+// Stage 2 (CompDotC over the renormalised pairs, Eq. 5.1 with n = 4): error
+// <= 16.1 u^2 (|n_x y| + |n_y x|) + 3.01 u^2 (|y| m_x + |x| m_y).
+// Thresholds carry a factor >= 5 (stage 1) and >= 60 (stage 2) of margin.
+__host__ __device__ __forceinline__ int d_sign(const ArcEft& a, double x, double y) {
+  double A = a.nx * y;
+  double Bv = a.ny * x;
+  double w0 = A - Bv;
+  double mag = __builtin_fabs(A) + __builtin_fabs(Bv);
+  double side = __builtin_fabs(y) * a.mx + __builtin_fabs(x) * a.my;
+  if (__builtin_fabs(w0) > 0x1p-49 * mag + 0x1p-96 * side) return sgn(w0);
+  dd p = two_prod(a.nx, y);
+  double s = p.lo, ph = p.hi;
+  dd h = two_prod(a.enx, y);
+  dd q = two_sum(ph, h.hi);
+  ph = q.hi;
+  s = s + (q.lo + h.lo);
+  h = two_prod(-a.ny, x);
+  q = two_sum(ph, h.hi);
+  ph = q.hi;
+  s = s + (q.lo + h.lo);
+  h = two_prod(-a.eny, x);
+  q = two_sum(ph, h.hi);
+  ph = q.hi;
+  s = s + (q.lo + h.lo);
+  double w = ph + s;
+  if (__builtin_fabs(w) > 0x1p-96 * (mag + side)) return sgn(w);
+  return UNDECIDED;
+}
+
+// Per-arc part of AccuX plus the direction signs.  d1/d2 may come back UNDECIDED.
+__host__ __device__ __forceinline__ void arc_eft(double x1, double y1, double z1, double x2,
+                                                 double y2, double z2, ArcEft& a) {
+  a.flags = 0;
+  a.d1 = a.d2 = 0;
+  a.z1 = z1;
+  a.z2 = z2;
+  if (!(finite(x1) && finite(y1) && finite(z1) && finite(x2) && finite(y2) && finite(z2))) {
+    a.flags = F_NONFINITE;
+    return;
+  }
+  // Alg. 8 lines 2-4 (normal n = x1 x x2).  A component is exactly zero iff both
+  // TwoProducts agree in both parts (fl(x) and x - fl(x) determine x).
+  dd px1 = two_prod(y1, z2), px2 = two_prod(z1, y2);
+  dd py1 = two_prod(z1, x2), py2 = two_prod(x1, z2);
+  dd pz1 = two_prod(x1, y2), pz2 = two_prod(y1, x2);
+  bool zx = px1.hi == px2.hi && px1.lo == px2.lo;
+  bool zy = py1.hi == py2.hi && py1.lo == py2.lo;
+  bool zz = pz1.hi == pz2.hi && pz1.lo == pz2.lo;
+  if (zx && zy && zz) {
+    a.flags = F_DEGEN_N;
+    return;
+  }
+  if (zx && zy) {
+    a.flags = F_HORIZ;
+    return;
+  }
+  {
+    dd t = two_sum(px1.hi, -px2.hi);
+    dd n = two_sum(t.hi, t.lo + (px1.lo - px2.lo));
+    a.nx = n.hi; a.enx = n.lo;
+    a.mx = __builtin_fabs(px1.hi) + __builtin_fabs(px2.hi);
+  }
+  {
+    dd t = two_sum(py1.hi, -py2.hi);
+    dd n = two_sum(t.hi, t.lo + (py1.lo - py2.lo));
+    a.ny = n.hi; a.eny = n.lo;
+    a.my = __builtin_fabs(py1.hi) + __builtin_fabs(py2.hi);
+  }
+  {
+    dd t = two_sum(pz1.hi, -pz2.hi);
+    dd n = two_sum(t.hi, t.lo + (pz1.lo - pz2.lo));
+    a.nz = n.hi; a.enz = n.lo;
+    a.mz = __builtin_fabs(pz1.hi) + __builtin_fabs(pz2.hi);
+  }
+  norms(a);  // Alg. 8 lines 5-6
+  dd fx = f_pair(a.nx, a.enx, a.nz, a.enz);
+  dd fy = f_pair(a.ny, a.eny, a.nz, a.enz);
+  a.Fx = fx.hi; a.eFx = fx.lo;
+  a.Fy = fy.hi; a.eFy = fy.lo;
+  a.nrm1 = __builtin_sqrt((x1 * x1 + y1 * y1) + z1 * z1);
+  a.nrm2 = __builtin_sqrt((x2 * x2 + y2 * y2) + z2 * z2);
+  a.d1 = d_sign(a, x1, y1);
+  a.d2 = d_sign(a, x2, y2);
+}
+
+// s^2 = |n_xy|^2 - |n|^2 z0^2 (Alg. 8 lines 7-11) and its certified sign.
+struct S2Eft {
+  double ss, ess;
+  int sign;  // -1, 0, 1 or UNDECIDED
+};
+
+// Error of (ss + ess) against the exact s^2 (first order):
+//   u^2 [14 S2 + 40 S3 z0^2 + 6.02 (1 + z0^2) sum_i |n_i| m_i]
+// from Alg. 7 (<= 11 u^2 S2 and 14 u^2 S3 over the renormalised normal), the normal error
+// (3.01 u^2 m_i per component), CompDotC over four terms (Eq. 5.1, 16 u^2 S3 z0^2) and the
+// compensation sum.  The filter uses 2^-96 = 1024 u^2 per term: a factor >= 25 of margin.
+__host__ __device__ __forceinline__ S2Eft s2_eft(const ArcEft& a, double z0) {
+  dd C = two_prod(z0, z0);
+  dd p = two_prod(a.S3, C.hi);  // Alg. 1 over {S3, S3, s3, s3} . {C, eC, C, eC}
+  double ph = p.hi, s = p.lo;
+  dd h = two_prod(a.S3, C.lo);
+  dd q = two_sum(ph, h.hi);
+  ph = q.hi;
+  s = s + (q.lo + h.lo);
+  h = two_prod(a.s3, C.hi);
+  q = two_sum(ph, h.hi);
+  ph = q.hi;
+  s = s + (q.lo + h.lo);
+  h = two_prod(a.s3, C.lo);
+  q = two_sum(ph, h.hi);
+  ph = q.hi;
+  s = s + (q.lo + h.lo);
+  dd E = two_sum(a.S2, -ph);
+  double e = (a.s2 - s) + E.lo;
+  dd r = fast_two_sum(E.hi, e);
+  S2Eft o;
+  o.ss = r.hi;
+  o.ess = r.lo;
+  double side = __builtin_fabs(a.nx) * a.mx + __builtin_fabs(a.ny) * a.my +
+                __builtin_fabs(a.nz) * a.mz;
+  double B = 0x1p-96 * (a.S2 + a.S3 * C.hi + (1.0 + C.hi) * side);
+  o.sign = r.hi > B ? 1 : (r.hi < -B ? -1 : UNDECIDED);
+  return o;
+}
+
+// sign(z0 - z/|x|) for one endpoint, or UNDECIDED (then the exact answer is
+// sgn(z0) * sign(z0^2 |x|^2 - z^2)).
+// Stage 1: t = fl(|z0| nrm - |z|) with nrm = fl(|x|) (relative error <= 2.51 u):
+//          error <= u |t| + 2.51 u |z0| |x|; threshold 16 u |z0| nrm.
+// Stage 2: z0^2 |x|^2 - z^2 as CompDotC over 14 exact terms (Eq. 5.1: <= 196 u^2 times the
+//          sum of magnitudes); threshold 2^-92 = 16384 u^2 times that sum.
+__host__ __device__ __forceinline__ int height_cmp(double z0, double z, double nrm, double x,
+                                                   double y, dd C) {
+  if (z0 == 0.0) return -sgn(z);
+  if (z == 0.0 || ((z0 > 0.0) != (z > 0.0))) return sgn(z0);
+  double az0 = __builtin_fabs(z0);
+  double t = __builtin_fma(az0, nrm, -__builtin_fabs(z));
+  if (__builtin_fabs(t) > 0x1p-49 * az0 * nrm) return sgn(z0) * sgn(t);
+  dd X = two_prod(x, x), Y = two_prod(y, y), Z = two_prod(z, z);
+  double ph, s;
+  dd p = two_prod(C.hi, X.hi);
+  ph = p.hi;
+  s = p.lo;
+#define SPHINT_CDC_STEP(A, B)            \
+  {                                      \
+    dd hh = two_prod((A), (B));          \
+    dd qq = two_sum(ph, hh.hi);          \
+    ph = qq.hi;                          \
+    s = s + (qq.lo + hh.lo);             \
+  }
+  SPHINT_CDC_STEP(C.hi, X.lo)
+  SPHINT_CDC_STEP(C.lo, X.hi)
+  SPHINT_CDC_STEP(C.lo, X.lo)
+  SPHINT_CDC_STEP(C.hi, Y.hi)
+  SPHINT_CDC_STEP(C.hi, Y.lo)
+  SPHINT_CDC_STEP(C.lo, Y.hi)
+  SPHINT_CDC_STEP(C.lo, Y.lo)
+  SPHINT_CDC_STEP(C.hi, Z.hi)
+  SPHINT_CDC_STEP(C.hi, Z.lo)
+  SPHINT_CDC_STEP(C.lo, Z.hi)
+  SPHINT_CDC_STEP(C.lo, Z.lo)
+  SPHINT_CDC_STEP(-1.0, Z.hi)
+  SPHINT_CDC_STEP(-1.0, Z.lo)
+#undef SPHINT_CDC_STEP
+  double w = ph + s;
+  if (__builtin_fabs(w) > 0x1p-92 * (C.hi * nrm * nrm + Z.hi)) return sgn(z0) * sgn(w);
+  return UNDECIDED;
+}
+
+// Alg. 2 (CompDot) over six precomputed TwoProducts, in Alg. 8's term order.
+__host__ __device__ __forceinline__ double comp_dot6(dd t0, dd t1, dd t2, dd t3, dd t4, dd t5) {
+  double p = t0.hi, s = t0.lo;
+  dd q = two_sum(p, t1.hi); p = q.hi; s = s + (q.lo + t1.lo);
+  q = two_sum(p, t2.hi); p = q.hi; s = s + (q.lo + t2.lo);
+  q = two_sum(p, t3.hi); p = q.hi; s = s + (q.lo + t3.lo);
+  q = two_sum(p, t4.hi); p = q.hi; s = s + (q.lo + t4.lo);
+  q = two_sum(p, t5.hi); p = q.hi; s = s + (q.lo + t5.lo);
+  return p + s;
+}
+
+__host__ __device__ __forceinline__ dd neg(dd v) { return {-v.hi, -v.lo}; }
+
+// Alg. 8 lines 12, 17, 22-25 for the roots of o (o.count, o.r0, o.r1 already set).  The
+// TwoProducts do not depend on the root: the lower-sign root negates (s, e_s), which
+// negates the last four terms of each CompDot exactly.
+__host__ __device__ __forceinline__ void points_eft(const ArcEft& a, double z0, const S2Eft& s2,
+                                                    PairOut& o) {
+  dd sq = acc_sqrt(s2.ss, s2.ess);
+  dd ax0 = two_prod(a.Fx, z0), ax1 = two_prod(a.eFx, z0);
+  dd ax2 = two_prod(a.ny, sq.hi), ax3 = two_prod(a.eny, sq.hi);
+  dd ax4 = two_prod(a.ny, sq.lo), ax5 = two_prod(a.eny, sq.lo);
+  dd ay0 = two_prod(a.Fy, z0), ay1 = two_prod(a.eFy, z0);
+  dd ay2 = two_prod(a.nx, sq.hi), ay3 = two_prod(a.enx, sq.hi);
+  dd ay4 = two_prod(a.nx, sq.lo), ay5 = two_prod(a.enx, sq.lo);
+  for (int k = 0; k < o.count; ++k) {
+    bool plus = (k == 0 ? o.r0 : o.r1) == ROOT_PLUS;
+    double xn, yn;
+    if (plus) {
+      xn = comp_dot6(ax0, ax1, ax2, ax3, ax4, ax5);
+      yn = comp_dot6(ay0, ay1, neg(ay2), neg(ay3), neg(ay4), neg(ay5));
+    } else {
+      xn = comp_dot6(ax0, ax1, neg(ax2), neg(ax3), neg(ax4), neg(ax5));
+      yn = comp_dot6(ay0, ay1, ay2, ay3, ay4, ay5);
+    }
+    double px = -(xn / a.S2);
+    double py = -(yn / a.S2);
+    if (k == 0) {
+      o.px0 = px;
+      o.py0 = py;
+    } else {
+      o.px1 = px;
+      o.py1 = py;
+    }
+  }
+}
+
+// ====================================================================== pair drivers
+
+// resolve(need, fn) must run fn() on every caller with need == true (the GPU runs them one
+// lane at a time per wavefront; the CPU build runs them at once).  All callers of one
+// wavefront must reach every resolve call.
+template <class Resolve>
+__host__ __device__ __forceinline__ PairOut eval_eft(bool valid, double x1, double y1, double z1,
+                                                     double x2, double y2, double z2, double z0,
+                                                     double* arena, Resolve&& resolve) {
+  ArcEft A;
+  A.flags = F_NONFINITE;
+  A.d1 = A.d2 = 0;
+  if (valid) arc_eft(x1, y1, z1, x2, y2, z2, A);
+  bool live = valid && A.flags == 0;
+  unsigned extra = 0;
+  auto exact = [&](int which) {
+    int r = exact_sign(which, x1, y1, z1, x2, y2, z2, z0, arena);
+    extra |= F_FALLBACK;
+    if (r == 2) {
+      extra |= F_INTERNAL;
+      r = 0;
+    }
+    return r;
+  };
+  resolve(live && (A.d1 == UNDECIDED || A.d2 == UNDECIDED), [&] {
+    if (A.d1 == UNDECIDED) A.d1 = exact(PRED_D1);
+    if (A.d2 == UNDECIDED) A.d2 = exact(PRED_D2);
+  });
+  PairOut o;
+  o.count = 0;
+  o.r0 = o.r1 = 0;
+  o.px0 = o.py0 = o.px1 = o.py1 = 0.0;
+  o.flags = valid ? A.flags : 0u;
+  if (live && !finite(z0)) {
+    o.flags = F_NONFINITE;
+    live = false;
+  }
+  S2Eft S;
+  S.sign = -1;
+  S.ss = S.ess = 0.0;
+  if (live) S = s2_eft(A, z0);
+  resolve(live && S.sign == UNDECIDED, [&] { S.sign = exact(PRED_S2); });
+  const bool exists = live && S.sign >= 0;
+  int c1 = 0, c2 = 0;
+  if (exists) {
+    dd C = two_prod(z0, z0);
+    c1 = height_cmp(z0, A.z1, A.nrm1, x1, y1, C);
+    c2 = height_cmp(z0, A.z2, A.nrm2, x2, y2, C);
+  }
+  resolve(exists && (c1 == UNDECIDED || c2 == UNDECIDED), [&] {
+    int sz = sgn(z0);
+    if (c1 == UNDECIDED) c1 = sz * exact(PRED_H1);
+    if (c2 == UNDECIDED) c2 = sz * exact(PRED_H2);
+  });
+  if (exists) {
+    const bool tangent = S.sign == 0;
+    o.flags = F_EXISTS | (tangent ? F_TANGENT : 0u);
+    o.count = hit_rule(A.d1, A.d2, c1, c2, tangent, o.r0, o.r1);
+    if (o.count) points_eft(A, z0, S, o);
+  }
+  o.flags |= extra;
+  return o;
+}
+
+__host__ __device__ __forceinline__ PairOut eval_naive(bool valid, double x1, double y1,
+                                                       double z1, double x2, double y2,
+                                                       double z2, double z0) {
+  PairOut o;
+  o.count = 0;
+  o.r0 = o.r1 = 0;
+  o.px0 = o.py0 = o.px1 = o.py1 = 0.0;
+  o.flags = 0;
+  if (!valid) return o;
+  ArcNaive A;
+  arc_naive(x1, y1, z1, x2, y2, z2, A);
+  return pair_naive(A, z0);
+}
+
+}  // namespace sphint

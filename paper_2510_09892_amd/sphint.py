@@ -1,0 +1,289 @@
+"""Python binding of libsphint (include/sphint.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels on the GPU.  PyTorch
+provides device memory and the current HIP stream; no torch arithmetic touches the data.
+Importing works without a GPU (for symbol checks); calls need a ROCm device and raise if
+the library was not built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(PKG, "libsphint.so")
+
+NAIVE = 0
+EFT = 1
+MODES = {"naive": NAIVE, "naive_fp64": NAIVE, "eft": EFT, "eft_fp64": EFT, NAIVE: NAIVE, EFT: EFT}
+
+OK, E_INVAL, E_CAPACITY, E_HIP, E_NOMEM, E_DEVICE = range(6)
+F_EXISTS, F_TANGENT, F_DEGEN_N, F_HORIZ, F_NONFINITE = 1, 2, 4, 8, 16
+ROOT_PLUS, ROOT_MINUS = 0, 1
+
+EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
+           "sphint_set_profile_events",
+           "sphint_batch_plan_create", "sphint_batch_autotune", "sphint_batch_launch",
+           "sphint_batch_params", "sphint_plan_destroy", "sphint_status_string",
+           "sphint_version")
+
+
+class PtsSoA(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+
+
+class Hits(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("pair", ctypes.c_void_p),
+                ("root", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_arcs", ctypes.c_int64), ("n_lat", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("p1", PtsSoA), ("p2", PtsSoA), ("lat_z", ctypes.c_void_p),
+                ("lat_offsets", ctypes.c_void_p), ("lat_idx", ctypes.c_void_p),
+                ("out", Hits), ("out_count", ctypes.c_void_p), ("out_flags", ctypes.c_void_p),
+                ("out_total", ctypes.c_void_p)]
+
+
+class SphintError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """The loaded library (ctypes), with argument types set.  Raises if not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise SphintError(f"{LIBPATH} is missing: build it with python -m paper_2510_09892_amd.build")
+    lib = ctypes.CDLL(LIBPATH)
+    i64, vp, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    lib.sphint_arc_constlat.argtypes = [i64, PtsSoA, PtsSoA, vp, i64, vp, vp, i64, Hits, vp, vp,
+                                        vp, ctypes.c_int, vp, sz, vp]
+    lib.sphint_arc_constlat.restype = ctypes.c_int
+    lib.sphint_workspace_size.argtypes = [i64]
+    lib.sphint_workspace_size.restype = sz
+    lib.sphint_set_profile_events.argtypes = [vp, vp]
+    lib.sphint_set_profile_events.restype = ctypes.c_int
+    lib.sphint_check.argtypes = [vp, i64, i64]
+    lib.sphint_check.restype = ctypes.c_int
+    lib.sphint_batch_plan_create.argtypes = [ctypes.POINTER(MeshDesc), ctypes.c_int,
+                                             ctypes.c_int, ctypes.POINTER(vp)]
+    lib.sphint_batch_plan_create.restype = ctypes.c_int
+    lib.sphint_batch_autotune.argtypes = [vp, ctypes.c_char_p, vp]
+    lib.sphint_batch_autotune.restype = ctypes.c_int
+    lib.sphint_batch_launch.argtypes = [vp, vp]
+    lib.sphint_batch_launch.restype = ctypes.c_int
+    lib.sphint_batch_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int)]
+    lib.sphint_batch_params.restype = ctypes.c_int
+    lib.sphint_plan_destroy.argtypes = [vp]
+    lib.sphint_plan_destroy.restype = None
+    lib.sphint_status_string.argtypes = [ctypes.c_int]
+    lib.sphint_status_string.restype = ctypes.c_char_p
+    lib.sphint_version.argtypes = []
+    lib.sphint_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status, what):
+    if status != OK:
+        msg = load().sphint_status_string(status).decode()
+        raise SphintError(f"{what}: {msg} (status {status})")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _soa(p):
+    """(x, y, z) device float64 tensors -> PtsSoA; accepts a (3, n) tensor too."""
+    import torch
+    if isinstance(p, torch.Tensor):
+        if p.dim() != 2 or p.shape[0] != 3:
+            raise SphintError("endpoints must be (x, y, z) tensors or a (3, n) tensor")
+        p = (p[0], p[1], p[2])
+    for t in p:
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise SphintError("endpoint components must be contiguous float64 CUDA tensors")
+    return PtsSoA(p[0].data_ptr(), p[1].data_ptr(), p[2].data_ptr()), len(p[0])
+
+
+class Output:
+    """Caller-owned device buffers for one call (reusable across calls of the same size)."""
+
+    def __init__(self, nnz, capacity=None, flags=True, device="cuda"):
+        import torch
+        cap = 2 * nnz if capacity is None else int(capacity)
+        self.nnz = nnz
+        self.capacity = cap
+        self.x = torch.empty(cap, dtype=torch.float64, device=device)
+        self.y = torch.empty(cap, dtype=torch.float64, device=device)
+        self.pair = torch.empty(cap, dtype=torch.int64, device=device)
+        self.root = torch.empty(cap, dtype=torch.uint8, device=device)
+        self.count = torch.empty(nnz, dtype=torch.uint8, device=device)
+        self.flags = torch.empty(nnz, dtype=torch.uint8, device=device) if flags else None
+        self.total = torch.zeros(1, dtype=torch.int64, device=device)
+        ws = int(load().sphint_workspace_size(nnz))
+        # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=device)
+        self.ws_bytes = ws
+
+    def hits(self):
+        """Synchronises; returns (x, y, pair, root) trimmed to the total."""
+        t = int(self.total.item())
+        if t > self.capacity:
+            raise SphintError(f"capacity {self.capacity} < {t} hits")
+        return self.x[:t], self.y[:t], self.pair[:t], self.root[:t]
+
+    def check(self):
+        """Synchronises; raises if the kernel reported an internal limit or overflowed."""
+        t = int(self.total.item())
+        _check(load().sphint_check(ctypes.c_void_p(self.workspace.data_ptr()), t, self.capacity),
+               "sphint_check")
+        return t
+
+    def hits_struct(self):
+        return Hits(self.x.data_ptr(), self.y.data_ptr(), self.pair.data_ptr(),
+                    self.root.data_ptr(), self.capacity)
+
+
+def arc_constlat(p1, p2, lat_z, lat_offsets=None, lat_idx=None, mode="eft", out=None,
+                 stream=None):
+    """Enqueue sphint_arc_constlat on the current (or given) stream; returns the Output.
+
+    Dense form: lat_z has one latitude per arc.  CSR form: lat_offsets (int64, n_arcs + 1)
+    and lat_idx (int32, nnz) index into lat_z.  Nothing is synchronised.
+    """
+    import torch
+    lib = load()
+    s1, n_arcs = _soa(p1)
+    s2, n2 = _soa(p2)
+    if n2 != n_arcs:
+        raise SphintError("p1 and p2 differ in length")
+    if lat_z.dtype != torch.float64 or not lat_z.is_cuda:
+        raise SphintError("lat_z must be a float64 CUDA tensor")
+    if lat_offsets is None:
+        nnz = n_arcs
+    else:
+        if lat_offsets.dtype != torch.int64 or lat_idx is None or lat_idx.dtype != torch.int32:
+            raise SphintError("CSR form needs int64 lat_offsets and int32 lat_idx")
+        nnz = len(lat_idx)
+    if out is None:
+        out = Output(nnz, device=lat_z.device)
+    if out.nnz != nnz:
+        raise SphintError("output buffers sized for a different number of pairs")
+    st = lib.sphint_arc_constlat(n_arcs, s1, s2, _ptr(lat_z), len(lat_z), _ptr(lat_offsets),
+                                 _ptr(lat_idx), nnz, out.hits_struct(), _ptr(out.count),
+                                 _ptr(out.flags), _ptr(out.total), MODES[mode],
+                                 _ptr(out.workspace), out.ws_bytes, _stream(stream))
+    _check(st, "sphint_arc_constlat")
+    return out
+
+
+class KernelTimer:
+    """HIP events the library records around its main kernel (sphint_set_profile_events).
+
+    ``arm(k)`` selects event pair k for the next call; ``durations_ms()`` synchronises and
+    returns the kernel time of every armed pair.
+    """
+
+    def __init__(self, n):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.ev = []
+        for _ in range(n):
+            a, b = ctypes.c_void_p(), ctypes.c_void_p()
+            if self.hip.hipEventCreate(ctypes.byref(a)) or self.hip.hipEventCreate(ctypes.byref(b)):
+                raise SphintError("hipEventCreate failed")
+            self.ev.append((a, b))
+        self.armed = []
+
+    def arm(self, k):
+        a, b = self.ev[k]
+        _check(load().sphint_set_profile_events(a, b), "sphint_set_profile_events")
+        self.armed.append(k)
+
+    def disarm(self):
+        _check(load().sphint_set_profile_events(None, None), "sphint_set_profile_events")
+
+    def durations_ms(self):
+        out = []
+        for k in self.armed:
+            a, b = self.ev[k]
+            self.hip.hipEventSynchronize(b)
+            ms = ctypes.c_float()
+            if self.hip.hipEventElapsedTime(ctypes.byref(ms), a, b):
+                raise SphintError("hipEventElapsedTime failed")
+            out.append(ms.value)
+        return out
+
+    def close(self):
+        self.disarm()
+        for a, b in self.ev:
+            self.hip.hipEventDestroy(a)
+            self.hip.hipEventDestroy(b)
+        self.ev = []
+
+
+class BatchPlan:
+    """sphint_batch_* over a list of meshes (each a dict of device tensors + Output)."""
+
+    def __init__(self, meshes, mode="eft"):
+        lib = load()
+        self._keep = meshes
+        arr = (MeshDesc * len(meshes))()
+        for k, m in enumerate(meshes):
+            s1, n_arcs = _soa(m["p1"])
+            s2, _ = _soa(m["p2"])
+            out = m["out"]
+            off = m.get("lat_offsets")
+            arr[k] = MeshDesc(n_arcs, len(m["lat_z"]), out.nnz, s1, s2, m["lat_z"].data_ptr(),
+                              off.data_ptr() if off is not None else None,
+                              m["lat_idx"].data_ptr() if off is not None else None,
+                              out.hits_struct(), out.count.data_ptr(),
+                              out.flags.data_ptr() if out.flags is not None else None,
+                              out.total.data_ptr())
+        h = ctypes.c_void_p()
+        _check(lib.sphint_batch_plan_create(arr, len(meshes), MODES[mode], ctypes.byref(h)),
+               "sphint_batch_plan_create")
+        self.handle = h
+
+    def autotune(self, cache_path=None, stream=None):
+        c = cache_path.encode() if cache_path else None
+        _check(load().sphint_batch_autotune(self.handle, c, _stream(stream)), "sphint_batch_autotune")
+
+    def launch(self, stream=None):
+        _check(load().sphint_batch_launch(self.handle, _stream(stream)), "sphint_batch_launch")
+
+    def params(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(load().sphint_batch_params(self.handle, ctypes.byref(a), ctypes.byref(b)),
+               "sphint_batch_params")
+        return a.value, b.value
+
+    def close(self):
+        if self.handle:
+            load().sphint_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

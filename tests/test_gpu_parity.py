@@ -1,0 +1,215 @@
+"""GPU parity: libsphint's kernels (through the C-ABI) against the oracle.
+
+EFT mode: hit counts, roots and flags exactly equal to the exact oracle; points equal to
+the oracle's binary64 AccuX replica bit for bit and within 4 * 2^-53 (max-norm) of the
+exact points.  Naive mode: counts, roots, flags and points equal to the oracle's binary64
+Eq. (2.2) replica bit for bit.  Sizes span several 256-pair tiles and a ragged tail.
+"""
+
+import math
+import sys
+from decimal import Decimal
+
+import numpy as np
+import pytest
+
+from oracle import batch as OB, geometry as G
+from paper_2510_09892_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+FLAG_MASK = 31
+
+
+def note(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+def to_dev(torch, arrays):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]
+
+
+def gpu_dense(torch, soa, mode, capacity=None):
+    from paper_2510_09892_amd import sphint
+    x1, y1, z1, x2, y2, z2, z0 = to_dev(torch, soa)
+    out = sphint.Output(len(z0), capacity=capacity)
+    sphint.arc_constlat((x1, y1, z1), (x2, y2, z2), z0, mode=mode, out=out)
+    torch.cuda.synchronize()
+    total = out.check() if capacity is None else int(out.total.item())
+    res = dict(total=total, count=out.count.cpu().numpy(), flags=out.flags.cpu().numpy())
+    k = min(total, out.capacity)
+    res.update(x=out.x[:k].cpu().numpy(), y=out.y[:k].cpu().numpy(),
+               pair=out.pair[:k].cpu().numpy(), root=out.root[:k].cpu().numpy())
+    return res
+
+
+def check_eft(res, soa, exact=None):
+    ex = exact or OB.exact(*soa)
+    np.testing.assert_array_equal(res["count"], ex.count)
+    np.testing.assert_array_equal(res["flags"] & FLAG_MASK, ex.flags)
+    assert res["total"] == ex.total
+    np.testing.assert_array_equal(res["pair"], np.array(ex.hit_pair, dtype=np.int64))
+    np.testing.assert_array_equal(res["root"], np.array(ex.hit_root, dtype=np.uint8))
+    rep = OB.accux_points(*soa, ex.roots)
+    flat = [p for pts in rep for p in pts]
+    np.testing.assert_array_equal(res["x"], np.array([p[0] for p in flat]))
+    np.testing.assert_array_equal(res["y"], np.array([p[1] for p in flat]))
+    worst = 0.0
+    for x, y, px, py in zip(res["x"], res["y"], ex.hit_x, ex.hit_y):
+        e = max(abs(Decimal(float(x)) - px), abs(Decimal(float(y)) - py)) / Decimal(U)
+        worst = max(worst, float(e))
+    assert worst <= 4.0, worst
+    return worst
+
+
+def check_naive(res, soa):
+    ref = OB.naive_fp64(*soa)
+    np.testing.assert_array_equal(res["count"], ref.count)
+    np.testing.assert_array_equal(res["flags"], ref.flags)
+    assert res["total"] == ref.total
+    np.testing.assert_array_equal(res["pair"], np.array(ref.hit_pair, dtype=np.int64))
+    np.testing.assert_array_equal(res["root"], np.array(ref.hit_root, dtype=np.uint8))
+    np.testing.assert_array_equal(res["x"], np.array(ref.hit_x))
+    np.testing.assert_array_equal(res["y"], np.array(ref.hit_y))
+
+
+# ------------------------------------------------------------------ dense workloads
+
+@pytest.mark.parametrize("n", [1, 255, 257, 20_011])
+def test_dense_uniform_eft(torch_cuda, n):
+    P = inputs.uniform_arcs(n, seed_tag=100 + n % 97)
+    note(f"dense uniform eft n={n}")
+    check_eft(gpu_dense(torch_cuda, P.soa(), "eft"), P.soa())
+
+
+def test_dense_ill_conditioned_eft(torch_cuda):
+    P = inputs.ill_conditioned(24_001, seed_tag=101)
+    note("dense ill-conditioned eft n=24001")
+    check_eft(gpu_dense(torch_cuda, P.soa(), "eft"), P.soa())
+
+
+@pytest.mark.parametrize("maker", ["uniform", "ill"])
+def test_dense_naive_bit_exact(torch_cuda, maker):
+    P = inputs.uniform_arcs(20_011, seed_tag=102) if maker == "uniform" else \
+        inputs.ill_conditioned(24_001, seed_tag=103)
+    note(f"dense naive {maker}")
+    check_naive(gpu_dense(torch_cuda, P.soa(), "naive"), P.soa())
+
+
+def _edge_soa():
+    import itertools
+    verts = [v for v in itertools.product((-1.0, 0.0, 1.0), repeat=3) if any(v)]
+    rows = [(*a, *b, z) for a in verts for b in verts
+            for z in (-1.0, -0.5, 0.0, 0.375, 1.0, 0.7071067811865476)]
+    rows += [
+        (1.0, 0.0, 0.0, 0.0, 1.0, 1.0, math.nan),
+        (math.inf, 0.0, 0.0, 0.0, 1.0, 1.0, 0.0),
+        (0.0, 0.0, 0.0, 0.0, 1.0, 1.0, 0.0),
+        (1.0, 2.0, 3.0, 2.0, 4.0, 6.0, 0.5),
+        (1.0, 0.0, -1.0, 0.0, 1.0, 1.0, 1.5),
+        (1.0, 0.0, 3.0, -1.0, 0.0, 2.0, 1.0),
+    ]
+    g = np.random.Generator(np.random.PCG64(104))
+    for _ in range(200):  # endpoint heights exactly representable (0.6) and 1 ulp around
+        k = 2.0 ** int(g.integers(-3, 4))
+        t = g.uniform(0, 2 * math.pi)
+        x1 = (0.8 * k * math.cos(t), 0.8 * k * math.sin(t), 0.6 * k)
+        x2 = tuple(float(v) for v in g.standard_normal(3))
+        zh = x1[2] / math.sqrt(sum(v * v for v in x1))
+        for z0 in (zh, math.nextafter(zh, 2), math.nextafter(zh, -2)):
+            rows.append((*x1, *x2, z0))
+    a = np.array(rows)
+    return [a[:, k].copy() for k in range(7)]
+
+
+def test_dense_edge_cases(torch_cuda):
+    """Exact ties, tangencies, degenerate and non-finite inputs (exact expansions path)."""
+    soa = _edge_soa()
+    note(f"dense edge cases eft n={len(soa[0])}")
+    res = gpu_dense(torch_cuda, soa, "eft")
+    check_eft(res, soa)
+    assert np.any(res["flags"] & 32)   # the exact expansion path ran on the GPU
+    note("dense edge cases naive")
+    check_naive(gpu_dense(torch_cuda, soa, "naive"), soa)
+
+
+def test_dense_empty(torch_cuda):
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    out = sphint.Output(0)
+    out.total.fill_(123)
+    note("dense empty")
+    sphint.arc_constlat((e, e, e), (e, e, e), e, mode="eft", out=out)
+    torch.cuda.synchronize()
+    assert int(out.total.item()) == 0
+
+
+def test_capacity_overflow_reports_total(torch_cuda):
+    P = inputs.uniform_arcs(5000, seed_tag=105)
+    note("dense capacity overflow")
+    res = gpu_dense(torch_cuda, P.soa(), "eft", capacity=1000)
+    ex = OB.exact(*P.soa())
+    assert res["total"] == ex.total > 1000
+    np.testing.assert_array_equal(res["pair"], np.array(ex.hit_pair[:1000], dtype=np.int64))
+
+
+def test_deterministic(torch_cuda):
+    P = inputs.ill_conditioned(50_000, seed_tag=106)
+    note("determinism")
+    a = gpu_dense(torch_cuda, P.soa(), "eft")
+    b = gpu_dense(torch_cuda, P.soa(), "eft")
+    for k in ("count", "flags", "x", "y", "pair", "root"):
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+
+
+# ------------------------------------------------------------------ CSR
+
+def gpu_csr(torch, mesh, mode):
+    from paper_2510_09892_amd import sphint
+    x1, y1, z1, x2, y2, z2 = to_dev(torch, mesh.soa())
+    lz, off, idx = to_dev(torch, (mesh.lat_z, mesh.lat_offsets, mesh.lat_idx))
+    out = sphint.Output(mesh.nnz)
+    sphint.arc_constlat((x1, y1, z1), (x2, y2, z2), lz, off, idx, mode=mode, out=out)
+    torch.cuda.synchronize()
+    total = out.check()
+    return dict(total=total, count=out.count.cpu().numpy(), flags=out.flags.cpu().numpy(),
+                x=out.x[:total].cpu().numpy(), y=out.y[:total].cpu().numpy(),
+                pair=out.pair[:total].cpu().numpy(), root=out.root[:total].cpu().numpy())
+
+
+@pytest.mark.parametrize("mode", ["eft", "naive"])
+def test_csr_random_mesh(torch_cuda, mode):
+    m = inputs.random_mesh(inputs.rng(107), 3000, 300, d_hi=0.05)
+    assert m.nnz > 5 * 256
+    note(f"csr random mesh {mode} arcs={m.n_arcs} nnz={m.nnz}")
+    res = gpu_csr(torch_cuda, m, mode)
+    soa = m.expand().soa()
+    (check_eft if mode == "eft" else check_naive)(res, soa)
+
+
+def test_csr_cubed_sphere_small(torch_cuda):
+    m = inputs.cubed_sphere(ne=24, n_lat=1800)
+    note(f"csr cubed sphere ne=24 nnz={m.nnz}")
+    res = gpu_csr(torch_cuda, m, "eft")
+    check_eft(res, m.expand().soa())
+
+
+def test_csr_bad_latitude_index_is_flagged(torch_cuda):
+    m = inputs.random_mesh(inputs.rng(108), 200, 50)
+    m.lat_idx[::7] = 10_000          # out of range: must become NONFINITE, not an OOB read
+    note("csr out-of-range lat_idx")
+    res = gpu_csr(torch_cuda, m, "eft")
+    bad = np.zeros(m.nnz, bool)
+    bad[::7] = True
+    assert np.all(res["flags"][bad] == 16) and np.all(res["count"][bad] == 0)

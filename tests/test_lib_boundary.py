@@ -1,0 +1,81 @@
+"""The C-ABI library without a GPU: exports, pure calls and argument validation.
+
+Every function include/sphint.h declares must be exported by libsphint.so; calls that
+fail validation return SPHINT_E_INVAL before any HIP call, so they run on a CPU host.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2510_09892_amd import sphint
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sphint.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(sphint_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("sphint_arc_constlat", "sphint_workspace_size", "sphint_batch_plan_create",
+              "sphint_batch_autotune", "sphint_batch_launch", "sphint_plan_destroy",
+              "sphint_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sphint.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(sphint.EXPORTS)
+
+
+def test_pure_calls():
+    lib = sphint.load()
+    assert lib.sphint_version().decode().startswith("sphint")
+    assert lib.sphint_status_string(0).decode() == "ok"
+    assert lib.sphint_workspace_size(0) == 256 + 8
+    assert lib.sphint_workspace_size(256) == 256 + 8
+    assert lib.sphint_workspace_size(257) == 256 + 16
+    assert lib.sphint_workspace_size(10_000_000) == 256 + 8 * 39063
+
+
+def _call(**kw):
+    lib = sphint.load()
+    d = dict(n=4, p1=sphint.PtsSoA(1, 2, 3), p2=sphint.PtsSoA(4, 5, 6), lat_z=7, n_lat=4,
+             off=None, idx=None, nnz=4, out=sphint.Hits(8, 9, 10, 11, 8), count=12, flags=None,
+             total=13, mode=1, ws=256, ws_bytes=1 << 20, stream=None)
+    d.update(kw)
+    return lib.sphint_arc_constlat(d["n"], d["p1"], d["p2"], d["lat_z"], d["n_lat"], d["off"],
+                                   d["idx"], d["nnz"], d["out"], d["count"], d["flags"],
+                                   d["total"], d["mode"], d["ws"], d["ws_bytes"], d["stream"])
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=-1), dict(nnz=5), dict(n_lat=3), dict(mode=7), dict(total=None),
+    dict(ws=None), dict(ws=260), dict(ws_bytes=8), dict(count=None),
+    dict(p1=sphint.PtsSoA(1, None, 3)), dict(out=sphint.Hits(None, 9, 10, 11, 8)),
+    dict(off=100, idx=None, nnz=3), dict(off=100, idx=200, nnz=3, n_lat=0),
+    dict(out=sphint.Hits(8, 9, 10, 11, -1)),
+])
+def test_invalid_arguments_rejected_before_launch(bad):
+    assert _call(**bad) == sphint.E_INVAL
+
+
+def test_batch_rejects_bad_arguments():
+    lib = sphint.load()
+    h = ctypes.c_void_p()
+    assert lib.sphint_batch_plan_create(None, 0, 1, ctypes.byref(h)) == sphint.E_INVAL
+    arr = (sphint.MeshDesc * 1)()
+    arr[0].n_arcs = -1
+    assert lib.sphint_batch_plan_create(arr, 1, 1, ctypes.byref(h)) == sphint.E_INVAL
+    assert lib.sphint_batch_launch(None, None) == sphint.E_INVAL
+    assert lib.sphint_set_profile_events(ctypes.c_void_p(1), None) == sphint.E_INVAL
