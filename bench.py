@@ -112,6 +112,12 @@ def main():
     sphint.load()
     log(f"[bench] generating {args.n} ill-conditioned arcs")
     P = inputs.ill_conditioned(args.n, seed_tag=1)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before any GPU call: the oracle's worker processes are forked from this one
+        log(f"[bench] cpu baseline: oracle on {args.cpu_sample} pairs")
+        cpu = cpu_baseline(P, inputs, args.cpu_sample)
+        log(f"[bench] cpu baseline {cpu['value']:.0f} pairs/s on {cpu['cores']} workers")
     dev = [torch.from_numpy(a).cuda() for a in P.soa()]
     torch.cuda.synchronize()
 
@@ -185,9 +191,8 @@ def main():
     if not args.no_latency:
         log("[bench] latency, 1e5 uniform arcs")
         line["latency_1e5"] = latency_small(torch, sphint, inputs)
-    if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline: oracle on {args.cpu_sample} pairs")
-        line["cpu_baseline"] = cpu_baseline(P, inputs, args.cpu_sample)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

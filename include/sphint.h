@@ -145,8 +145,10 @@ typedef struct sphint_plan sphint_plan;
 
 /*
  * Plan for running many meshes in one persistent launch.  Copies the descriptors to the
- * device (the one allocation of the plan, owned by it) and prepares the tile schedule.
- * Each mesh's results equal a sphint_arc_constlat call on that mesh alone.
+ * device (the plan's own allocations: descriptor table, tile table, scan states) and
+ * prepares the tile schedule.  All meshes of a plan must have the same form (all CSR or all
+ * dense), else SPHINT_E_INVAL.  Each mesh's results equal a sphint_arc_constlat call on that
+ * mesh alone.
  */
 sphint_status sphint_batch_plan_create(const sphint_mesh_desc *meshes, int n_meshes,
                                        sphint_mode mode, sphint_plan **plan);
@@ -158,10 +160,14 @@ sphint_status sphint_batch_autotune(sphint_plan *plan, const char *cache_path, v
 /* Launches the plan on `stream`: the first launch captures the init and persistent kernels
  * into a HIP graph (on a stream of the plan's own), every launch replays it. */
 sphint_status sphint_batch_launch(sphint_plan *plan, void *stream);
-/* Schedule of the plan: pairs per thread (tile = 256 * pairs_per_thread pairs) and resident
- * workgroups per compute unit of the persistent grid (0: one workgroup per tile). */
+/* Schedule of the plan: pairs per lane (a wavefront tile is 64 * pairs_per_thread pairs) and
+ * workgroups per compute unit of the persistent grid (0: as many as the CU holds; never more,
+ * since the grid's wavefronts must all be resident). */
 sphint_status sphint_batch_params(const sphint_plan *plan, int *pairs_per_thread,
                                   int *wg_per_cu);
+/* Sets the schedule by hand (pairs_per_thread 1, 2 or 4; wg_per_cu >= 0, capped at what a CU
+ * holds) instead of the autotuner's choice; the next launch re-captures the graph. */
+sphint_status sphint_batch_set_params(sphint_plan *plan, int pairs_per_thread, int wg_per_cu);
 void sphint_plan_destroy(sphint_plan *plan);
 
 const char *sphint_status_string(sphint_status s);

@@ -25,13 +25,48 @@ __global__ void k_init(uint32_t* ws, uint64_t* status, int64_t ntiles, int64_t* 
   for (int64_t k = t; k < ntiles; k += (int64_t)gridDim.x * blockDim.x) status[k] = 0ull;
 }
 
-constexpr int PPT_SINGLE = 1;  // pairs per thread of single calls
+constexpr int WPPT_SINGLE = 4;       // pairs per lane of single calls (wavefront tile = 256)
+constexpr int WG_PER_CU_SINGLE = 4;  // resident workgroups per CU of the persistent grid
 
 thread_local hipEvent_t prof_start = nullptr, prof_stop = nullptr;
 
-template <int MODE>
+// Compute units of the current device (queried once per device).
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
+
+// Workgroups of k_intersect_w<MODE, WPPT_SINGLE, CSR> one CU holds at once (queried once).
+template <int MODE, bool CSR>
+int resident_per_cu() {
+  static int cached = 0;
+  if (!cached) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_intersect_w<MODE, WPPT_SINGLE, CSR>,
+                                                     BLOCK, 0) != hipSuccess || b <= 0)
+      b = 1;
+    cached = b;
+  }
+  return cached;
+}
+
+template <int MODE, bool CSR>
 hipError_t launch_main(const KArgs& k, hipStream_t st) {
-  hipLaunchKernelGGL((k_intersect<MODE, PPT_SINGLE>), dim3((unsigned)k.ntiles), dim3(BLOCK), 0,
+  int per_cu = resident_per_cu<MODE, CSR>();
+  if (per_cu > WG_PER_CU_SINGLE) per_cu = WG_PER_CU_SINGLE;
+  int64_t grid = (int64_t)per_cu * device_cus();
+  const int64_t need = (k.ntiles + 1 + NWAVE - 1) / NWAVE;  // + the scanner wavefront
+  if (grid > need) grid = need;
+  hipLaunchKernelGGL((k_intersect_w<MODE, WPPT_SINGLE, CSR>), dim3((unsigned)grid), dim3(BLOCK), 0,
                      st, k);
   return hipGetLastError();
 }
@@ -39,7 +74,7 @@ hipError_t launch_main(const KArgs& k, hipStream_t st) {
 }  // namespace
 
 extern "C" size_t sphint_workspace_size(int64_t nnz) {
-  int64_t t = tiles_for(nnz < 0 ? 0 : nnz);
+  int64_t t = wave_tiles_for(nnz < 0 ? 0 : nnz, 1);  // the most tiles any schedule uses
   return WS_HEADER + 8 * (size_t)(t > 0 ? t : 1);
 }
 
@@ -57,7 +92,7 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
   if (v != SPHINT_OK) return v;
   if (!workspace || !aligned256(workspace) || workspace_bytes < sphint_workspace_size(nnz))
     return SPHINT_E_INVAL;
-  const int64_t ntiles = tiles_for(nnz);
+  const int64_t ntiles = wave_tiles_for(nnz, WPPT_SINGLE);
   if (ntiles > 0x7fffffffLL) return SPHINT_E_INVAL;
   hipStream_t st = (hipStream_t)stream;
   uint32_t* ws = (uint32_t*)workspace;
@@ -74,7 +109,10 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
   KArgs k = make_args(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out, out_count,
                       out_flags, out_total, ws, status, ntiles);
   if (prof_start && hipEventRecord(prof_start, st) != hipSuccess) return SPHINT_E_HIP;
-  hipError_t e = mode == SPHINT_EFT_FP64 ? launch_main<1>(k, st) : launch_main<0>(k, st);
+  const bool csr = lat_offsets != nullptr;
+  hipError_t e;
+  if (mode == SPHINT_EFT_FP64) e = csr ? launch_main<1, true>(k, st) : launch_main<1, false>(k, st);
+  else e = csr ? launch_main<0, true>(k, st) : launch_main<0, false>(k, st);
   if (e == hipSuccess && prof_stop) e = hipEventRecord(prof_stop, st);
   return e == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
 }

@@ -7,7 +7,7 @@
 // sphint_arc_constlat call on that mesh alone.  Tiles of one mesh are taken in increasing
 // order, which keeps the look-back's waits on tiles that are already running.
 //
-// Schedule parameters: pairs per thread (tile = 256 * ppt pairs) and the number of resident
+// Schedule parameters: pairs per lane (wavefront tile = 64 * ppt pairs) and the number of resident
 // workgroups per CU; sphint_batch_autotune times the candidates and keeps the fastest.  The
 // init kernel and the persistent kernel are captured once into a HIP graph and replayed.
 #pragma clang fp contract(off)
@@ -26,34 +26,34 @@
 
 using namespace sphint;
 
-template <int MODE, int PPT>
+template <int MODE, int PPT, bool CSR>
 __global__ __launch_bounds__(BLOCK) void k_batch(const KArgs* __restrict__ args,
                                                  const int64_t* __restrict__ tile_base,
-                                                 int n_meshes, int64_t total_tiles,
-                                                 uint32_t* counter) {
-  __shared__ TileShared<MODE, PPT> sh;
-  __shared__ int64_t s_tile;
-  __shared__ int s_mesh;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      int64_t t = (int64_t)atomicAdd(counter, 1u);
-      int lo = 0, hi = n_meshes - 1;
-      while (lo < hi) {  // largest mesh whose first tile is <= t
-        int mid = (lo + hi + 1) >> 1;
-        if (tile_base[mid] <= t) lo = mid;
-        else hi = mid - 1;
-      }
-      s_tile = t;
-      s_mesh = lo;
+                                                 int n_meshes, int64_t total_tiles) {
+  __shared__ WgShared<MODE, PPT> sh;
+  if (threadIdx.x == 0) sh.lock = 0;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  const int64_t gw = (int64_t)blockIdx.x * NWAVE + wave;
+  const int64_t W = (int64_t)gridDim.x * NWAVE - 1;
+  if (gw == W) {  // the scanner follows the global tile order: mesh after mesh
+    for (int m = 0; m < n_meshes; ++m) {
+      const KArgs a = args[m];
+      scan_tiles<scan_k<PPT>()>(a.status, a.ntiles, a.ototal, a.ws,
+                                reinterpret_cast<uint64_t*>(&sh.stage[wave]));
     }
-    __syncthreads();
-    const int64_t t = s_tile;
-    if (t >= total_tiles) break;  // every workgroup leaves once the tiles run out
-    const int m = s_mesh;
-    const KArgs a = args[m];
-    run_tile<MODE, PPT>(a, t - tile_base[m], sh);
-    __syncthreads();
+    return;
   }
+  int64_t t = gw;
+  int mesh = 0;  // tiles only increase, so the mesh index only moves forward
+  wave_loop<MODE, PPT, CSR>(args, sh, [&](int& m, int64_t& tile) {
+    if (t >= total_tiles) return false;
+    while (mesh + 1 < n_meshes && tile_base[mesh + 1] <= t) ++mesh;
+    m = mesh;
+    tile = t - tile_base[mesh];
+    t += W;
+    return true;
+  });
 }
 
 __global__ void k_batch_init(uint32_t* ws, uint64_t* status, int64_t total_tiles,
@@ -74,7 +74,7 @@ struct sphint_plan {
   int cus = 1;
   // schedule
   int ppt = 1;
-  int wg_per_cu = 0;  // 0: one workgroup per tile (non-persistent grid)
+  int wg_per_cu = 0;  // resident workgroups per CU (0: as many as fit)
   // device state
   KArgs* d_args = nullptr;
   int64_t* d_tile_base = nullptr;
@@ -82,30 +82,32 @@ struct sphint_plan {
   size_t ws_bytes = 0;
   std::vector<int64_t> tile_base;
   int64_t total_tiles = 0;
+  bool csr = false;  // every mesh of a plan has the same form
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
-template <int MODE, int PPT>
+template <int MODE, int PPT, bool CSR>
 int max_resident() {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MODE, PPT>, BLOCK, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MODE, PPT, CSR>, BLOCK, 0) !=
       hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
 }
 
-int resident_per_cu(sphint_mode mode, int ppt) {
+template <bool CSR>
+int resident_per_cu_form(sphint_mode mode, int ppt) {
   if (mode == SPHINT_EFT_FP64) {
-    if (ppt == 1) return max_resident<1, 1>();
-    if (ppt == 2) return max_resident<1, 2>();
-    return max_resident<1, 4>();
+    if (ppt == 1) return max_resident<1, 1, CSR>();
+    if (ppt == 2) return max_resident<1, 2, CSR>();
+    return max_resident<1, 4, CSR>();
   }
-  if (ppt == 1) return max_resident<0, 1>();
-  if (ppt == 2) return max_resident<0, 2>();
-  return max_resident<0, 4>();
+  if (ppt == 1) return max_resident<0, 1, CSR>();
+  if (ppt == 2) return max_resident<0, 2, CSR>();
+  return max_resident<0, 4, CSR>();
 }
 
 void drop_graph(sphint_plan* p) {
@@ -119,7 +121,7 @@ sphint_status layout(sphint_plan* p) {
   const int n = (int)p->meshes.size();
   p->tile_base.assign(n + 1, 0);
   for (int m = 0; m < n; ++m)
-    p->tile_base[m + 1] = p->tile_base[m] + tiles_for(p->meshes[m].nnz, p->ppt);
+    p->tile_base[m + 1] = p->tile_base[m] + wave_tiles_for(p->meshes[m].nnz, p->ppt);
   p->total_tiles = p->tile_base[n];
   if (p->total_tiles > 0x7fffffffLL) return SPHINT_E_INVAL;
   const size_t need = WS_HEADER + 8 * (size_t)(p->total_tiles > 0 ? p->total_tiles : 1);
@@ -146,10 +148,19 @@ sphint_status layout(sphint_plan* p) {
   return SPHINT_OK;
 }
 
+int resident_per_cu(const sphint_plan* p, int ppt) {
+  return p->csr ? resident_per_cu_form<true>(p->mode, ppt)
+                : resident_per_cu_form<false>(p->mode, ppt);
+}
+
 template <int MODE, int PPT>
 void launch_batch(const sphint_plan* p, unsigned grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_batch<MODE, PPT>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
-                     p->d_tile_base, (int)p->meshes.size(), p->total_tiles, (uint32_t*)p->d_ws);
+  if (p->csr)
+    hipLaunchKernelGGL((k_batch<MODE, PPT, true>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
+                       p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
+  else
+    hipLaunchKernelGGL((k_batch<MODE, PPT, false>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
+                       p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
 }
 
 // Enqueues init + persistent kernel on st (no graph).
@@ -164,11 +175,11 @@ sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_init, dim3(ib), dim3(256), 0, st, ws, status, p->total_tiles,
                      p->d_args, n);
   if (p->total_tiles > 0) {
-    int64_t grid = p->total_tiles;
-    if (p->wg_per_cu > 0) {
-      int64_t res = (int64_t)p->wg_per_cu * p->cus;
-      if (res < grid) grid = res;
-    }
+    // every wavefront of the grid must be resident at once (see k_batch)
+    const int res = resident_per_cu(p, p->ppt);
+    const int per_cu = p->wg_per_cu > 0 && p->wg_per_cu < res ? p->wg_per_cu : res;
+    int64_t grid = (p->total_tiles + 1 + NWAVE - 1) / NWAVE;  // + the scanner
+    if ((int64_t)per_cu * p->cus < grid) grid = (int64_t)per_cu * p->cus;
     const bool eft = p->mode == SPHINT_EFT_FP64;
     if (p->ppt == 1) eft ? launch_batch<1, 1>(p, (unsigned)grid, st) : launch_batch<0, 1>(p, (unsigned)grid, st);
     else if (p->ppt == 2) eft ? launch_batch<1, 2>(p, (unsigned)grid, st) : launch_batch<0, 2>(p, (unsigned)grid, st);
@@ -201,10 +212,12 @@ extern "C" sphint_status sphint_batch_plan_create(const sphint_mesh_desc* meshes
     sphint_status v = validate(d.n_arcs, d.p1, d.p2, d.lat_z, d.n_lat, d.lat_offsets,
                                d.lat_idx, d.nnz, d.out, d.out_count, d.out_total);
     if (v != SPHINT_OK) return v;
+    if ((d.lat_offsets != nullptr) != (meshes[0].lat_offsets != nullptr)) return SPHINT_E_INVAL;
   }
   sphint_plan* p = new (std::nothrow) sphint_plan();
   if (!p) return SPHINT_E_NOMEM;
   p->mode = mode;
+  p->csr = meshes[0].lat_offsets != nullptr;
   p->meshes.assign(meshes, meshes + n_meshes);
   (void)hipGetDevice(&p->device);
   hipDeviceProp_t prop;
@@ -214,8 +227,8 @@ extern "C" sphint_status sphint_batch_plan_create(const sphint_mesh_desc* meshes
     sphint_plan_destroy(p);
     return SPHINT_E_HIP;
   }
-  p->ppt = 1;
-  p->wg_per_cu = resident_per_cu(mode, 1);
+  p->ppt = 4;
+  p->wg_per_cu = 0;
   sphint_status s = layout(p);
   if (s != SPHINT_OK) {
     sphint_plan_destroy(p);
@@ -285,9 +298,10 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
   const int ppts[3] = {1, 2, 4};
   for (int pi = 0; pi < 3; ++pi) {
     const int ppt = ppts[pi];
-    const int res = resident_per_cu(p->mode, ppt);
-    const int wgs[4] = {0, res, res > 1 ? res / 2 : 1, 2 * res};
+    const int res = resident_per_cu(p, ppt);
+    const int wgs[4] = {res, res > 1 ? res - 1 : 1, res > 2 ? res / 2 : 1, 1};
     for (int wi = 0; wi < 4; ++wi) {
+      if (wi > 0 && wgs[wi] == wgs[wi - 1]) continue;
       p->ppt = ppt;
       p->wg_per_cu = wgs[wi];
       sphint_status s = layout(p);
@@ -328,6 +342,16 @@ extern "C" sphint_status sphint_batch_params(const sphint_plan* p, int* pairs_pe
   if (pairs_per_thread) *pairs_per_thread = p->ppt;
   if (wg_per_cu) *wg_per_cu = p->wg_per_cu;
   return SPHINT_OK;
+}
+
+extern "C" sphint_status sphint_batch_set_params(sphint_plan* p, int pairs_per_thread,
+                                                 int wg_per_cu) {
+  if (!p || !(pairs_per_thread == 1 || pairs_per_thread == 2 || pairs_per_thread == 4) ||
+      wg_per_cu < 0)
+    return SPHINT_E_INVAL;
+  p->ppt = pairs_per_thread;
+  p->wg_per_cu = wg_per_cu;
+  return layout(p);
 }
 
 extern "C" void sphint_plan_destroy(sphint_plan* p) {

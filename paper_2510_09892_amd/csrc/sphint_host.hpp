@@ -13,6 +13,11 @@ inline int64_t tiles_for(int64_t nnz, int ppt = 1) {
   return nnz > 0 ? (nnz + per - 1) / per : 0;
 }
 
+inline int64_t wave_tiles_for(int64_t nnz, int wppt) {
+  const int64_t per = (int64_t)64 * wppt;
+  return nnz > 0 ? (nnz + per - 1) / per : 0;
+}
+
 inline bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
 // Argument checks shared by the single-call and batched paths.

@@ -17,8 +17,11 @@ namespace sphint {
 constexpr int BLOCK = 256;
 constexpr int NWAVE = BLOCK / 64;
 constexpr size_t WS_HEADER = 256;  // counter + error word, padded
-constexpr uint64_t ST_AGG = 1, ST_PREFIX = 2;
-constexpr long SPIN_LIMIT = 1L << 24;  // bounded wait: ~seconds, far beyond any real wait
+constexpr uint64_t ST_AGG = 1, ST_PREFIX = 2;  // tile states (value << 2) | state
+// Bounded waits: a wait gives up after WAIT_TICKS of the 100 MHz real-time counter (2 s, far
+// beyond any real wait), sets ERR_SPIN, and every later wait of the launch gives up at once,
+// so a launch always ends (with the error reported by sphint_check).
+constexpr uint64_t WAIT_TICKS = 200000000ull;
 enum : uint32_t { ERR_SPIN = 1u, ERR_EXACT = 2u };
 
 struct KArgs {
@@ -62,152 +65,407 @@ __device__ __forceinline__ int64_t find_arc(const int64_t* __restrict__ off, int
   return lo;
 }
 
-// Single-pass decoupled look-back: publish this tile's aggregate, sum predecessors until
-// one with an inclusive prefix, publish the inclusive prefix.  Returns the exclusive prefix.
-__device__ __forceinline__ int64_t look_back(uint64_t* status, int64_t tile, int64_t agg,
-                                             uint32_t* ws) {
-  if (tile == 0) {
-    __hip_atomic_store(status, ((uint64_t)agg << 2) | ST_PREFIX, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    return 0;
+
+// Ordered offsets across tiles.  A compute wavefront publishes its tile's hit count
+// (aggregate) and later reads its exclusive prefix; one scanner wavefront per launch walks the
+// tile states in order, up to K * 64 tiles per pass, and publishes the prefix of every tile
+// whose predecessors have all reported; waiting wavefronts read only their own word.
+
+// True when this wait must give up (timed out, or another wait of the launch did).
+__device__ __forceinline__ bool wait_expired(uint64_t t0, unsigned& polls, uint32_t* ws) {
+  if ((++polls & 63u) == 0 &&
+      (__hip_atomic_load(ws + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_SPIN))
+    return true;
+  if (__builtin_amdgcn_s_memrealtime() - t0 > WAIT_TICKS) {
+    atomicOr(ws + 1, ERR_SPIN);
+    return true;
   }
-  __hip_atomic_store(status + tile, ((uint64_t)agg << 2) | ST_AGG, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-  int64_t excl = 0;
-  int64_t j = tile - 1;
-  long spins = 0;
-  while (j >= 0) {
-    uint64_t w = __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t st = w & 3u;
-    if (st == 0) {
-      if (++spins > SPIN_LIMIT) {
-        atomicOr(ws + 1, ERR_SPIN);
+  return false;
+}
+
+// Waits (lane 0 polls, bounded) until the scanner has published the tile's exclusive prefix.
+__device__ __forceinline__ int64_t wait_prefix(uint64_t* status, int64_t tile, uint32_t* ws) {
+  const int lane = __lane_id();
+  uint64_t w = 0;
+  if (lane == 0) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    unsigned polls = 0;
+    for (;;) {
+      w = __hip_atomic_load(status + tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((w & 3u) == ST_PREFIX) break;
+      if (wait_expired(t0, polls, ws)) {
+        w = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  w = __shfl(w, 0, 64);
+  return (int64_t)(w >> 2);
+}
+
+// The scanner (one whole wavefront) for tiles [0, ntiles) of one call: publishes each tile's
+// exclusive prefix in place of its aggregate and finally the call's total.  A pass reads
+// K * 64 consecutive tile states with contiguous 512-byte loads, transposes them through
+// `lds` (64 * (K + 1) words, padded against bank conflicts) so that lane l holds tiles
+// t + K l ... t + K l + K - 1, sums within lanes, scans the 64 lane sums once, and writes
+// the prefixes back the same way.
+template <int K>
+__device__ __forceinline__ int64_t lane_scan(int64_t v) {  // inclusive scan over the wave
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+template <int K>
+__device__ __forceinline__ void scan_tiles(uint64_t* status, int64_t ntiles, int64_t* ototal,
+                                           uint32_t* ws, uint64_t* lds) {
+  const int lane = __lane_id();
+  constexpr int P = K + 1;  // padded row length of the transposed layout
+  int64_t t = 0, run = 0;   // first tile without a prefix, hits before it
+  uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  unsigned polls = 0;
+  while (t < ntiles) {
+    // coalesced loads: word k * 64 + lane of the window goes to lds[(q / K) * P + q % K]
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int q = k * 64 + lane;
+      const int64_t j = t + q;
+      uint64_t w = 0;
+      if (j < ntiles) w = __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      lds[(q / K) * P + q % K] = w;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int ready = 0;  // leading entries of this lane that have reported
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t w = lds[lane * P + k];
+      if (ready == k && (w & 3u) == ST_AGG) {
+        ++ready;
+        sum += (int64_t)(w >> 2);
+      }
+    }
+    const unsigned long long full = __ballot(ready == K);
+    const int L = full == ~0ull ? 64 : __ffsll(~full) - 1;  // first incomplete lane
+    const int64_t v = lane <= L ? sum : 0;
+    const int64_t inc = lane_scan<K>(v);
+    int64_t ex = run + inc - v;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {  // prefixes (state 0 = not published) back into lds
+      const uint64_t w = lds[lane * P + k];
+      uint64_t outw = 0;
+      if (lane <= L && k < ready) {
+        outw = ((uint64_t)ex << 2) | ST_PREFIX;
+        ex += (int64_t)(w >> 2);
+      }
+      lds[lane * P + k] = outw;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int q = k * 64 + lane;
+      const uint64_t w = lds[(q / K) * P + q % K];
+      if (w) __hip_atomic_store(status + t + q, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const int rL = __shfl(ready, L < 64 ? L : 63, 64);
+    const int64_t advance = (int64_t)K * L + (L < 64 ? rL : 0);
+    run += __shfl(inc, L < 64 ? L : 63, 64);
+    __builtin_amdgcn_wave_barrier();
+    if (advance == 0) {
+      bool quit = false;
+      if (lane == 0) quit = wait_expired(t0, polls, ws);
+      if (__shfl((int)quit, 0, 64)) break;
+      __builtin_amdgcn_s_sleep(2);
       continue;
     }
-    excl += (int64_t)(w >> 2);
-    if (st == ST_PREFIX) break;
-    --j;
+    t0 = __builtin_amdgcn_s_memrealtime();
+    t += advance;
   }
-  __hip_atomic_store(status + tile, ((uint64_t)(excl + agg) << 2) | ST_PREFIX,
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return excl;
+  if (lane == 0) *ototal = run;
 }
 
-// Shared state of one workgroup while it processes a tile.
-template <int MODE, int PPT>
-struct TileShared {
-  double arena[MODE ? NWAVE : 1][MODE ? xp::ARENA : 1];
-  int64_t prefix, arc_lo, arc_hi;
-  int wtot[PPT][NWAVE];
+// ---------------------------------------------------------------- wavefront tiles
+//
+// A tile of WPPT * 64 consecutive pairs belongs to one wavefront: row j holds pairs
+// base + 64 j + lane.  The wavefront evaluates the tile (writing counts and flags at once),
+// publishes its hit count, and only then writes out the hits of its PREVIOUS tile, whose
+// offset has had a whole tile's evaluation to arrive; those hits wait in an LDS buffer of
+// the wavefront, from which they are copied to the output in contiguous (coalesced) runs.
+
+// Hits of one pending tile, compacted in pair order.
+template <int WPPT>
+struct WaveStage {
+  double x[2 * 64 * WPPT];
+  double y[2 * 64 * WPPT];
+  uint16_t pair[2 * 64 * WPPT];  // pair offset within the tile
+  uint8_t root[2 * 64 * WPPT];
 };
 
-// Evaluates pairs [tile * BLOCK * PPT, +BLOCK * PPT) of call `a` and writes their counts,
-// flags and compacted hits.  Pair base + j * BLOCK + tid goes to thread tid (coalesced
-// loads), so hits are ordered row j by row j.  All threads of the workgroup must call it.
-template <int MODE, int PPT>
-__device__ __forceinline__ void run_tile(const KArgs& a, int64_t tile, TileShared<MODE, PPT>& sh) {
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const bool csr = a.off != nullptr;
-  const int64_t base = tile * (int64_t)(BLOCK * PPT);
-  if (csr) {
-    if (tid == 0) sh.arc_lo = find_arc(a.off, 0, a.n_arcs - 1, base);
-    if (tid == BLOCK - 1) {
-      int64_t last = base + BLOCK * PPT - 1 < a.nnz ? base + BLOCK * PPT - 1 : a.nnz - 1;
-      sh.arc_hi = find_arc(a.off, 0, a.n_arcs - 1, last);
-    }
-    __syncthreads();
-  }
-  PairOut o[PPT];
-  int woff[PPT];
-  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    const int64_t i = base + (int64_t)j * BLOCK + tid;
-    const bool valid = i < a.nnz;
-    int64_t arc = i;
-    double z0 = 0.0;
-    if (csr) {
-      arc = valid ? find_arc(a.off, sh.arc_lo, sh.arc_hi, i) : 0;
-      if (valid) {
-        int32_t li = a.idx[i];
-        z0 = (li >= 0 && li < a.n_lat) ? a.lat_z[li] : __builtin_nan("");
-      }
-    } else if (valid) {
-      z0 = a.lat_z[i];
-    }
-    double x1 = 0, y1 = 0, z1 = 0, x2 = 0, y2 = 0, z2 = 0;
-    if (valid) {
-      x1 = a.x1[arc]; y1 = a.y1[arc]; z1 = a.z1[arc];
-      x2 = a.x2[arc]; y2 = a.y2[arc]; z2 = a.z2[arc];
-    }
-    if (MODE) {
-      o[j] = eval_eft(valid, x1, y1, z1, x2, y2, z2, z0, &sh.arena[MODE ? wave : 0][0],
-                      [](bool need, auto&& fn) { resolve_serial(need, fn); });
-      if (o[j].flags & F_INTERNAL) atomicOr(a.ws + 1, ERR_EXACT);
-    } else {
-      o[j] = eval_naive(valid, x1, y1, z1, x2, y2, z2, z0);
-    }
-    const int cnt = valid ? o[j].count : 0;
-    o[j].count = cnt;
-    const unsigned long long b1 = __ballot(cnt >= 1);
-    const unsigned long long b2 = __ballot(cnt >= 2);
-    woff[j] = __popcll(b1 & lt) + __popcll(b2 & lt);
-    if (lane == 0) sh.wtot[j][wave] = __popcll(b1) + __popcll(b2);
-  }
-  __syncthreads();
-  int boff[PPT];
-  int agg = 0;
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    boff[j] = agg;
-#pragma unroll
-    for (int w = 0; w < NWAVE; ++w) {
-      int t = sh.wtot[j][w];
-      boff[j] += w < wave ? t : 0;
-      agg += t;
-    }
-  }
-  if (tid == 0) sh.prefix = look_back(a.status, tile, agg, a.ws);
-  __syncthreads();
-  const int64_t prefix = sh.prefix;
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    const int64_t i = base + (int64_t)j * BLOCK + tid;
-    const int cnt = o[j].count;
-    const int64_t pos = prefix + boff[j] + woff[j];
-    if (i < a.nnz) {
-      a.ocount[i] = (uint8_t)cnt;
-      if (a.oflags) a.oflags[i] = (uint8_t)o[j].flags;
-    }
-    if (cnt >= 1 && pos < a.cap) {
-      a.ox[pos] = o[j].px0;
-      a.oy[pos] = o[j].py0;
-      a.opair[pos] = i;
-      a.oroot[pos] = (uint8_t)o[j].r0;
-    }
-    if (cnt >= 2 && pos + 1 < a.cap) {
-      a.ox[pos + 1] = o[j].px1;
-      a.oy[pos + 1] = o[j].py1;
-      a.opair[pos + 1] = i;
-      a.oroot[pos + 1] = (uint8_t)o[j].r1;
-    }
-  }
-  if (tid == 0 && tile == a.ntiles - 1) *a.ototal = prefix + agg;
+// Workgroup LDS: one staging buffer per wavefront and one exact-arithmetic arena shared by
+// the workgroup's wavefronts under a lock (exact evaluations are rare).
+// Tiles per scanner lane per pass: the scanner borrows its own (unused) staging buffer.
+template <int WPPT>
+constexpr int scan_k() {
+  return (int)(sizeof(WaveStage<WPPT>) / (64 * sizeof(uint64_t))) - 1;
 }
 
-// One workgroup per tile; tile ids in start order from the workspace counter.
-template <int MODE, int PPT>
-__global__ __launch_bounds__(BLOCK) void k_intersect(KArgs a) {
-  __shared__ TileShared<MODE, PPT> sh;
-  __shared__ int64_t s_tile;
-  if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(a.ws, 1u);
+template <int MODE, int WPPT>
+struct WgShared {
+  WaveStage<WPPT> stage[NWAVE];
+  double arena[MODE ? xp::ARENA : 1];
+  int lock;
+};
+
+__device__ __forceinline__ void lds_lock(int* l) {
+  while (atomicCAS(l, 0, 1) != 0) __builtin_amdgcn_s_sleep(1);
+}
+__device__ __forceinline__ void lds_unlock(int* l) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  atomicExch(l, 0);
+}
+
+// Results of the tile being evaluated, held in registers.
+template <int WPPT>
+struct TileRegs {
+  PairOut o[WPPT];
+  int woff[WPPT];
+  int agg;
+};
+
+// Inputs of one row (64 pairs, one per lane) of a tile.
+struct RowIn {
+  double x1, y1, z1, x2, y2, z2, z0;
+  int64_t i;
+  bool valid;
+};
+
+// Per-tile context for loading rows: the tile's first pair and, for CSR calls, the range
+// of arcs its pairs belong to.
+struct TileCtx {
+  int64_t base, arc_lo, arc_hi;
+};
+
+template <int WPPT, bool CSR>
+__device__ __forceinline__ TileCtx tile_ctx(const KArgs& a, int64_t tile) {
+  const int lane = __lane_id();
+  TileCtx c;
+  c.base = tile * (int64_t)(64 * WPPT);
+  c.arc_lo = c.arc_hi = 0;
+  if (CSR) {
+    int64_t first = c.base < a.nnz ? c.base : a.nnz - 1;
+    int64_t last = c.base + 64 * WPPT - 1 < a.nnz ? c.base + 64 * WPPT - 1 : a.nnz - 1;
+    int64_t v = 0;
+    if (lane == 0) v = find_arc(a.off, 0, a.n_arcs - 1, first);
+    if (lane == 1) v = find_arc(a.off, 0, a.n_arcs - 1, last);
+    c.arc_lo = __shfl(v, 0, 64);
+    c.arc_hi = __shfl(v, 1, 64);
+  }
+  return c;
+}
+
+// Loads one row without branches: lanes past the end read the last pair (and are marked
+// invalid), so the compiler can count outstanding loads exactly and the row fetched ahead
+// stays in flight while the current row is evaluated.
+template <bool CSR>
+__device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int j) {
+  RowIn r;
+  r.i = c.base + (int64_t)j * 64 + __lane_id();
+  r.valid = r.i < a.nnz;
+  const int64_t ii = r.valid ? r.i : a.nnz - 1;
+  int64_t arc = ii;
+  if (CSR) {
+    arc = find_arc(a.off, c.arc_lo, c.arc_hi, ii);
+    const int32_t li = a.idx[ii];
+    const bool ok = li >= 0 && li < a.n_lat;
+    const double z = a.lat_z[ok ? li : 0];
+    r.z0 = ok ? z : __builtin_nan("");
+  } else {
+    r.z0 = a.lat_z[ii];
+  }
+  r.x1 = a.x1[arc]; r.y1 = a.y1[arc]; r.z1 = a.z1[arc];
+  r.x2 = a.x2[arc]; r.y2 = a.y2[arc]; r.z2 = a.z2[arc];
+  return r;
+}
+
+// Evaluates one row already loaded, writes its counts and flags, and accumulates the
+// tile's in-order hit offsets.
+template <int MODE, int WPPT>
+__device__ __forceinline__ void eval_row(const KArgs& a, const RowIn& in, int j, TileRegs<WPPT>& r,
+                                         WgShared<MODE, WPPT>& sh) {
+  const int lane = __lane_id();
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  PairOut& o = r.o[j];
+  if (MODE) {
+    o = eval_eft(in.valid, in.x1, in.y1, in.z1, in.x2, in.y2, in.z2, in.z0, sh.arena,
+                 [&](bool need, auto&& fn) {
+                   resolve_serial(need, [&] {
+                     lds_lock(&sh.lock);
+                     fn();
+                     lds_unlock(&sh.lock);
+                   });
+                 });
+    if (o.flags & F_INTERNAL) atomicOr(a.ws + 1, ERR_EXACT);
+  } else {
+    o = eval_naive(in.valid, in.x1, in.y1, in.z1, in.x2, in.y2, in.z2, in.z0);
+  }
+  const int cnt = in.valid ? o.count : 0;
+  o.count = cnt;
+  if (in.valid) {
+    a.ocount[in.i] = (uint8_t)cnt;
+    if (a.oflags) a.oflags[in.i] = (uint8_t)o.flags;
+  }
+  const unsigned long long b1 = __ballot(cnt >= 1);
+  const unsigned long long b2 = __ballot(cnt >= 2);
+  if (j == 0) r.agg = 0;
+  r.woff[j] = r.agg + __popcll(b1 & lt) + __popcll(b2 & lt);
+  r.agg += __popcll(b1) + __popcll(b2);
+}
+
+// Moves the tile's hits from registers into the wavefront's staging buffer.
+template <int WPPT>
+__device__ __forceinline__ void stage_tile(const TileRegs<WPPT>& r, WaveStage<WPPT>& st) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int j = 0; j < WPPT; ++j) {
+    const PairOut& o = r.o[j];
+    const int p = r.woff[j];
+    const uint16_t off = (uint16_t)(j * 64 + lane);
+    if (o.count >= 1) {
+      st.x[p] = o.px0;
+      st.y[p] = o.py0;
+      st.pair[p] = off;
+      st.root[p] = (uint8_t)o.r0;
+    }
+    if (o.count >= 2) {
+      st.x[p + 1] = o.px1;
+      st.y[p + 1] = o.py1;
+      st.pair[p + 1] = off;
+      st.root[p + 1] = (uint8_t)o.r1;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Copies a staged tile's `count` hits to the output at offset `prefix` (coalesced).
+template <int WPPT>
+__device__ __forceinline__ void flush_tile(const KArgs& a, int64_t tile, int count, int64_t prefix,
+                                           const WaveStage<WPPT>& st) {
+  const int lane = __lane_id();
+  const int64_t base = tile * (int64_t)(64 * WPPT);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int k = lane; k < count; k += 64) {
+    const int64_t pos = prefix + k;
+    if (pos < a.cap) {
+      a.ox[pos] = st.x[k];
+      a.oy[pos] = st.y[k];
+      a.opair[pos] = base + st.pair[k];
+      a.oroot[pos] = st.root[k];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One wavefront's share of the tiles: tiles come from `next` (the KArgs index and local
+// tile, or false when done).  Loads run one row ahead of evaluation (the next tile's first
+// row is fetched while the current tile's last row is evaluated).  After a tile is evaluated
+// its hit count is published and the PREVIOUS tile's hits are written out.
+template <int MODE, int WPPT, bool CSR, class Next>
+__device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT>& sh, Next&& next) {
+  const int wave = threadIdx.x >> 6;
+  WaveStage<WPPT>& st = sh.stage[wave];
+  bool pending = false;
+  int pm = 0, pagg = 0;
+  int64_t ptile = 0;
+  int m = 0, m2 = 0;
+  int64_t tile = 0, tile2 = 0;
+  TileRegs<WPPT> r;
+  bool have = next(m, tile);
+  if (!have) return;
+  TileCtx ctx = tile_ctx<WPPT, CSR>(args[m], tile), ctx2;
+  RowIn cur = load_row<CSR>(args[m], ctx, 0), nxt;
+  while (have) {
+    const KArgs& a = args[m];
+    bool have2 = false;
+#pragma unroll
+    for (int j = 0; j < WPPT; ++j) {
+      if (j + 1 < WPPT) {
+        nxt = load_row<CSR>(a, ctx, j + 1);
+      } else {
+        // always fetch ahead; past the last tile the fetch repeats this tile (unused)
+        have2 = next(m2, tile2);
+        if (!have2) {
+          m2 = m;
+          tile2 = tile;
+        }
+        ctx2 = tile_ctx<WPPT, CSR>(args[m2], tile2);
+        nxt = load_row<CSR>(args[m2], ctx2, 0);
+      }
+      eval_row<MODE, WPPT>(a, cur, j, r, sh);
+      cur = nxt;
+    }
+    if (__lane_id() == 0)
+      __hip_atomic_store(a.status + tile, ((uint64_t)r.agg << 2) | ST_AGG, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    if (pending) {
+      const KArgs& pa = args[pm];
+      const int64_t prefix = wait_prefix(pa.status, ptile, pa.ws);
+      flush_tile<WPPT>(pa, ptile, pagg, prefix, st);
+    }
+    stage_tile<WPPT>(r, st);
+    pending = true;
+    pm = m;
+    ptile = tile;
+    pagg = r.agg;
+    have = have2;
+    m = m2;
+    tile = tile2;
+    ctx = ctx2;
+  }
+  if (pending) {
+    const KArgs& pa = args[pm];
+    const int64_t prefix = wait_prefix(pa.status, ptile, pa.ws);
+    flush_tile<WPPT>(pa, ptile, pagg, prefix, st);
+  }
+}
+
+// Persistent wavefronts with a static order.  The grid never exceeds what the device holds
+// at once, so every tile the scanner waits on belongs to a running wavefront; there is no
+// atomic tile counter (a single contended address serialises at tens of millions of
+// operations per second).  The last wavefront of the grid is the scanner; compute wavefront
+// c of the other W takes tiles c, c + W, c + 2W, ...
+template <int MODE, int WPPT, bool CSR>
+__global__ __launch_bounds__(BLOCK) void k_intersect_w(KArgs a) {
+  __shared__ WgShared<MODE, WPPT> sh;
+  if (threadIdx.x == 0) sh.lock = 0;
   __syncthreads();
-  run_tile<MODE, PPT>(a, s_tile, sh);
+  const int wave = threadIdx.x >> 6;
+  const int64_t gw = (int64_t)blockIdx.x * NWAVE + wave;
+  const int64_t W = (int64_t)gridDim.x * NWAVE - 1;
+  if (gw == W) {
+    scan_tiles<scan_k<WPPT>()>(a.status, a.ntiles, a.ototal, a.ws,
+                               reinterpret_cast<uint64_t*>(&sh.stage[wave]));
+    return;
+  }
+  int64_t t = gw;
+  wave_loop<MODE, WPPT, CSR>(&a, sh, [&](int& m, int64_t& tile) {
+    if (t >= a.ntiles) return false;
+    m = 0;
+    tile = t;
+    t += W;
+    return true;
+  });
 }
 
 }  // namespace sphint

@@ -331,29 +331,23 @@ __host__ __device__ __forceinline__ double comp_dot6(dd t0, dd t1, dd t2, dd t3,
 __host__ __device__ __forceinline__ dd neg(dd v) { return {-v.hi, -v.lo}; }
 
 // Alg. 8 lines 12, 17, 22-25 for the roots of o (o.count, o.r0, o.r1 already set).  The
-// TwoProducts do not depend on the root: the lower-sign root negates (s, e_s), which
-// negates the last four terms of each CompDot exactly.
+// lower-sign root is AccuX with (s, e_s) negated (negation is exact).  The two z0 terms of
+// each CompDot do not depend on the root and are formed once.
 __host__ __device__ __forceinline__ void points_eft(const ArcEft& a, double z0, const S2Eft& s2,
                                                     PairOut& o) {
-  dd sq = acc_sqrt(s2.ss, s2.ess);
-  dd ax0 = two_prod(a.Fx, z0), ax1 = two_prod(a.eFx, z0);
-  dd ax2 = two_prod(a.ny, sq.hi), ax3 = two_prod(a.eny, sq.hi);
-  dd ax4 = two_prod(a.ny, sq.lo), ax5 = two_prod(a.eny, sq.lo);
-  dd ay0 = two_prod(a.Fy, z0), ay1 = two_prod(a.eFy, z0);
-  dd ay2 = two_prod(a.nx, sq.hi), ay3 = two_prod(a.enx, sq.hi);
-  dd ay4 = two_prod(a.nx, sq.lo), ay5 = two_prod(a.enx, sq.lo);
+  const dd sq = acc_sqrt(s2.ss, s2.ess);
+  const dd fx0 = two_prod(a.Fx, z0), fx1 = two_prod(a.eFx, z0);
+  const dd fy0 = two_prod(a.Fy, z0), fy1 = two_prod(a.eFy, z0);
   for (int k = 0; k < o.count; ++k) {
-    bool plus = (k == 0 ? o.r0 : o.r1) == ROOT_PLUS;
-    double xn, yn;
-    if (plus) {
-      xn = comp_dot6(ax0, ax1, ax2, ax3, ax4, ax5);
-      yn = comp_dot6(ay0, ay1, neg(ay2), neg(ay3), neg(ay4), neg(ay5));
-    } else {
-      xn = comp_dot6(ax0, ax1, neg(ax2), neg(ax3), neg(ax4), neg(ax5));
-      yn = comp_dot6(ay0, ay1, ay2, ay3, ay4, ay5);
-    }
-    double px = -(xn / a.S2);
-    double py = -(yn / a.S2);
+    const bool plus = (k == 0 ? o.r0 : o.r1) == ROOT_PLUS;
+    const double sb = plus ? sq.hi : -sq.hi;
+    const double es = plus ? sq.lo : -sq.lo;
+    const double xn = comp_dot6(fx0, fx1, two_prod(a.ny, sb), two_prod(a.eny, sb),
+                                two_prod(a.ny, es), two_prod(a.eny, es));
+    const double yn = comp_dot6(fy0, fy1, two_prod(-a.nx, sb), two_prod(-a.enx, sb),
+                                two_prod(-a.nx, es), two_prod(-a.enx, es));
+    const double px = -(xn / a.S2);
+    const double py = -(yn / a.S2);
     if (k == 0) {
       o.px0 = px;
       o.py0 = py;

@@ -25,7 +25,8 @@ ROOT_PLUS, ROOT_MINUS = 0, 1
 EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_set_profile_events",
            "sphint_batch_plan_create", "sphint_batch_autotune", "sphint_batch_launch",
-           "sphint_batch_params", "sphint_plan_destroy", "sphint_status_string",
+           "sphint_batch_params", "sphint_batch_set_params", "sphint_plan_destroy",
+           "sphint_status_string",
            "sphint_version")
 
 
@@ -81,6 +82,8 @@ def load():
     lib.sphint_batch_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int)]
     lib.sphint_batch_params.restype = ctypes.c_int
+    lib.sphint_batch_set_params.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.sphint_batch_set_params.restype = ctypes.c_int
     lib.sphint_plan_destroy.argtypes = [vp]
     lib.sphint_plan_destroy.restype = None
     lib.sphint_status_string.argtypes = [ctypes.c_int]
@@ -276,6 +279,10 @@ class BatchPlan:
         _check(load().sphint_batch_params(self.handle, ctypes.byref(a), ctypes.byref(b)),
                "sphint_batch_params")
         return a.value, b.value
+
+    def set_params(self, pairs_per_thread, wg_per_cu):
+        _check(load().sphint_batch_set_params(self.handle, pairs_per_thread, wg_per_cu),
+               "sphint_batch_set_params")
 
     def close(self):
         if self.handle:

@@ -54,13 +54,13 @@ def gpu_dense(torch, soa, mode, capacity=None):
 
 
 def check_eft(res, soa, exact=None):
-    ex = exact or OB.exact(*soa)
+    ex = exact or OB.exact(*soa, workers=1)
     np.testing.assert_array_equal(res["count"], ex.count)
     np.testing.assert_array_equal(res["flags"] & FLAG_MASK, ex.flags)
     assert res["total"] == ex.total
     np.testing.assert_array_equal(res["pair"], np.array(ex.hit_pair, dtype=np.int64))
     np.testing.assert_array_equal(res["root"], np.array(ex.hit_root, dtype=np.uint8))
-    rep = OB.accux_points(*soa, ex.roots)
+    rep = OB.accux_points(*soa, ex.roots, workers=1)
     flat = [p for pts in rep for p in pts]
     np.testing.assert_array_equal(res["x"], np.array([p[0] for p in flat]))
     np.testing.assert_array_equal(res["y"], np.array([p[1] for p in flat]))
@@ -73,7 +73,7 @@ def check_eft(res, soa, exact=None):
 
 
 def check_naive(res, soa):
-    ref = OB.naive_fp64(*soa)
+    ref = OB.naive_fp64(*soa, workers=1)
     np.testing.assert_array_equal(res["count"], ref.count)
     np.testing.assert_array_equal(res["flags"], ref.flags)
     assert res["total"] == ref.total
@@ -159,7 +159,7 @@ def test_capacity_overflow_reports_total(torch_cuda):
     P = inputs.uniform_arcs(5000, seed_tag=105)
     note("dense capacity overflow")
     res = gpu_dense(torch_cuda, P.soa(), "eft", capacity=1000)
-    ex = OB.exact(*P.soa())
+    ex = OB.exact(*P.soa(), workers=1)
     assert res["total"] == ex.total > 1000
     np.testing.assert_array_equal(res["pair"], np.array(ex.hit_pair[:1000], dtype=np.int64))
 

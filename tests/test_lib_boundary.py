@@ -43,9 +43,9 @@ def test_pure_calls():
     assert lib.sphint_version().decode().startswith("sphint")
     assert lib.sphint_status_string(0).decode() == "ok"
     assert lib.sphint_workspace_size(0) == 256 + 8
-    assert lib.sphint_workspace_size(256) == 256 + 8
-    assert lib.sphint_workspace_size(257) == 256 + 16
-    assert lib.sphint_workspace_size(10_000_000) == 256 + 8 * 39063
+    assert lib.sphint_workspace_size(64) == 256 + 8
+    assert lib.sphint_workspace_size(65) == 256 + 16
+    assert lib.sphint_workspace_size(10_000_000) == 256 + 8 * 156250
 
 
 def _call(**kw):
