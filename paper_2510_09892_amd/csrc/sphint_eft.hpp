@@ -70,7 +70,8 @@ struct ArcEft {
   double mx, my, mz;                 // AccuDOP magnitudes
   double S2, s2, S3, s3;             // |n_xy|^2 and |n|^2 as pairs (Alg. 7)
   double Fx, eFx, Fy, eFy;           // n_x n_z and n_y n_z as pairs
-  double nrm1, nrm2;                 // binary64 |x1|, |x2| (filters only)
+  double n21, n22, zz1, zz2;         // binary64 |x1|^2, |x2|^2, z1^2, z2^2 (filters only)
+  double side;                       // sum |n_i| m_i (the s^2 filter's normal-error term)
   double z1, z2;
   int d1, d2;                        // exact signs of dz/dt at the endpoints
   unsigned flags;

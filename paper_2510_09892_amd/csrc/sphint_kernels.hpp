@@ -331,30 +331,25 @@ __device__ __forceinline__ void eval_row(const KArgs& a, const RowIn& in, int j,
   r.agg += __popcll(b1) + __popcll(b2);
 }
 
-// Moves the tile's hits from registers into the wavefront's staging buffer.
+// Moves row j's hits from registers into the wavefront's staging buffer.
 template <int WPPT>
-__device__ __forceinline__ void stage_tile(const TileRegs<WPPT>& r, WaveStage<WPPT>& st) {
+__device__ __forceinline__ void stage_row(const TileRegs<WPPT>& r, int j, WaveStage<WPPT>& st) {
   const int lane = __lane_id();
-#pragma unroll
-  for (int j = 0; j < WPPT; ++j) {
-    const PairOut& o = r.o[j];
-    const int p = r.woff[j];
-    const uint16_t off = (uint16_t)(j * 64 + lane);
-    if (o.count >= 1) {
-      st.x[p] = o.px0;
-      st.y[p] = o.py0;
-      st.pair[p] = off;
-      st.root[p] = (uint8_t)o.r0;
-    }
-    if (o.count >= 2) {
-      st.x[p + 1] = o.px1;
-      st.y[p + 1] = o.py1;
-      st.pair[p + 1] = off;
-      st.root[p + 1] = (uint8_t)o.r1;
-    }
+  const PairOut& o = r.o[j];
+  const int p = r.woff[j];
+  const uint16_t off = (uint16_t)(j * 64 + lane);
+  if (o.count >= 1) {
+    st.x[p] = o.px0;
+    st.y[p] = o.py0;
+    st.pair[p] = off;
+    st.root[p] = (uint8_t)o.r0;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  if (o.count >= 2) {
+    st.x[p + 1] = o.px1;
+    st.y[p + 1] = o.py1;
+    st.pair[p + 1] = off;
+    st.root[p + 1] = (uint8_t)o.r1;
+  }
 }
 
 // Copies a staged tile's `count` hits to the output at offset `prefix` (coalesced).
@@ -379,10 +374,14 @@ __device__ __forceinline__ void flush_tile(const KArgs& a, int64_t tile, int cou
 
 // One wavefront's share of the tiles: tiles come from `next` (the KArgs index and local
 // tile, or false when done).  Loads run one row ahead of evaluation (the next tile's first
-// row is fetched while the current tile's last row is evaluated).  After a tile is evaluated
-// its hit count is published and the PREVIOUS tile's hits are written out.
-template <int MODE, int WPPT, bool CSR, class Next>
+// row is fetched while the current tile's last row is evaluated).  A tile's hit count is
+// published when its last row is done; the previous tile's hits are written out after the
+// first FLUSH_AT rows of the next tile, which gives the scanner that much time to publish
+// its offset.  Rows evaluated after that point go straight to the staging buffer, so at most
+// FLUSH_AT rows of results are held in registers.
+template <int MODE, int WPPT, bool CSR, int FLUSH_AT, class Next>
 __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT>& sh, Next&& next) {
+  static_assert(FLUSH_AT >= 1 && FLUSH_AT <= WPPT, "flush point inside the tile");
   const int wave = threadIdx.x >> 6;
   WaveStage<WPPT>& st = sh.stage[wave];
   bool pending = false;
@@ -413,17 +412,24 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
         nxt = load_row<CSR>(args[m2], ctx2, 0);
       }
       eval_row<MODE, WPPT>(a, cur, j, r, sh);
+      if (j + 1 == FLUSH_AT) {
+        if (pending) {
+          const KArgs& pa = args[pm];
+          const int64_t prefix = wait_prefix(pa.status, ptile, pa.ws);
+          flush_tile<WPPT>(pa, ptile, pagg, prefix, st);
+        }
+#pragma unroll
+        for (int jj = 0; jj <= j; ++jj) stage_row<WPPT>(r, jj, st);
+      } else if (j + 1 > FLUSH_AT) {
+        stage_row<WPPT>(r, j, st);
+      }
       cur = nxt;
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     if (__lane_id() == 0)
       __hip_atomic_store(a.status + tile, ((uint64_t)r.agg << 2) | ST_AGG, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
-    if (pending) {
-      const KArgs& pa = args[pm];
-      const int64_t prefix = wait_prefix(pa.status, ptile, pa.ws);
-      flush_tile<WPPT>(pa, ptile, pagg, prefix, st);
-    }
-    stage_tile<WPPT>(r, st);
     pending = true;
     pm = m;
     ptile = tile;
@@ -438,6 +444,14 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
     const int64_t prefix = wait_prefix(pa.status, ptile, pa.ws);
     flush_tile<WPPT>(pa, ptile, pagg, prefix, st);
   }
+}
+
+// Rows evaluated before the previous tile is written out: one for the EFT evaluation
+// (registers are scarce, and a row takes long enough for the offset to arrive), the whole
+// tile for the short naive evaluation.
+template <int MODE, int WPPT>
+constexpr int flush_at() {
+  return MODE ? 1 : WPPT;
 }
 
 // Persistent wavefronts with a static order.  The grid never exceeds what the device holds
@@ -459,7 +473,7 @@ __global__ __launch_bounds__(BLOCK) void k_intersect_w(KArgs a) {
     return;
   }
   int64_t t = gw;
-  wave_loop<MODE, WPPT, CSR>(&a, sh, [&](int& m, int64_t& tile) {
+  wave_loop<MODE, WPPT, CSR, flush_at<MODE, WPPT>()>(&a, sh, [&](int& m, int64_t& tile) {
     if (t >= a.ntiles) return false;
     m = 0;
     tile = t;

@@ -35,6 +35,7 @@ enum : unsigned {
   F_NONFINITE = 16u,
   F_FALLBACK = 32u,  // diagnostic: an exact expansion evaluation decided this pair
   F_INTERNAL = 64u,  // an exact evaluation exceeded its arena (outside the input domain)
+  F_NEEDEXACT = 128u,  // internal: a filter could not decide; re-evaluate with exact signs
 };
 enum : int { ROOT_PLUS = 0, ROOT_MINUS = 1 };
 constexpr int UNDECIDED = 2;
@@ -177,7 +178,7 @@ __host__ __device__ __forceinline__ int d_sign(const ArcEft& a, double x, double
   return UNDECIDED;
 }
 
-// Per-arc part of AccuX plus the direction signs.  d1/d2 may come back UNDECIDED.
+// Per-arc part of AccuX (the direction signs are decided by the caller).
 __host__ __device__ __forceinline__ void arc_eft(double x1, double y1, double z1, double x2,
                                                  double y2, double z2, ArcEft& a) {
   a.flags = 0;
@@ -227,10 +228,11 @@ __host__ __device__ __forceinline__ void arc_eft(double x1, double y1, double z1
   dd fy = f_pair(a.ny, a.eny, a.nz, a.enz);
   a.Fx = fx.hi; a.eFx = fx.lo;
   a.Fy = fy.hi; a.eFy = fy.lo;
-  a.nrm1 = __builtin_sqrt((x1 * x1 + y1 * y1) + z1 * z1);
-  a.nrm2 = __builtin_sqrt((x2 * x2 + y2 * y2) + z2 * z2);
-  a.d1 = d_sign(a, x1, y1);
-  a.d2 = d_sign(a, x2, y2);
+  a.n21 = (x1 * x1 + y1 * y1) + z1 * z1;
+  a.n22 = (x2 * x2 + y2 * y2) + z2 * z2;
+  a.zz1 = z1 * z1;
+  a.zz2 = z2 * z2;
+  a.side = __builtin_fabs(a.nx) * a.mx + __builtin_fabs(a.ny) * a.my + __builtin_fabs(a.nz) * a.mz;
 }
 
 // s^2 = |n_xy|^2 - |n|^2 z0^2 (Alg. 8 lines 7-11) and its certified sign.
@@ -266,26 +268,25 @@ __host__ __device__ __forceinline__ S2Eft s2_eft(const ArcEft& a, double z0) {
   S2Eft o;
   o.ss = r.hi;
   o.ess = r.lo;
-  double side = __builtin_fabs(a.nx) * a.mx + __builtin_fabs(a.ny) * a.my +
-                __builtin_fabs(a.nz) * a.mz;
-  double B = 0x1p-96 * (a.S2 + a.S3 * C.hi + (1.0 + C.hi) * side);
+  double B = 0x1p-96 * (a.S2 + a.S3 * C.hi + (1.0 + C.hi) * a.side);
   o.sign = r.hi > B ? 1 : (r.hi < -B ? -1 : UNDECIDED);
   return o;
 }
 
 // sign(z0 - z/|x|) for one endpoint, or UNDECIDED (then the exact answer is
-// sgn(z0) * sign(z0^2 |x|^2 - z^2)).
-// Stage 1: t = fl(|z0| nrm - |z|) with nrm = fl(|x|) (relative error <= 2.51 u):
-//          error <= u |t| + 2.51 u |z0| |x|; threshold 16 u |z0| nrm.
+// sgn(z0) * sign(z0^2 |x|^2 - z^2)).  Only the same-sign case needs arithmetic:
+// Stage 1: t = fl(C n2 - zz) (one FMA) with C = fl(z0^2), n2 = fl(|x|^2) (three products and
+//          two sums: relative error <= 3.01 u), zz = fl(z^2): error <= 4.02 u C n2 + u zz +
+//          u |t|; threshold 2^-49 (C n2 + zz) = 16 u (...).
 // Stage 2: z0^2 |x|^2 - z^2 as CompDotC over 14 exact terms (Eq. 5.1: <= 196 u^2 times the
 //          sum of magnitudes); threshold 2^-92 = 16384 u^2 times that sum.
-__host__ __device__ __forceinline__ int height_cmp(double z0, double z, double nrm, double x,
-                                                   double y, dd C) {
+__host__ __device__ __forceinline__ int height_cmp(double z0, double z, double n2, double zz,
+                                                   double x, double y, dd C) {
   if (z0 == 0.0) return -sgn(z);
   if (z == 0.0 || ((z0 > 0.0) != (z > 0.0))) return sgn(z0);
-  double az0 = __builtin_fabs(z0);
-  double t = __builtin_fma(az0, nrm, -__builtin_fabs(z));
-  if (__builtin_fabs(t) > 0x1p-49 * az0 * nrm) return sgn(z0) * sgn(t);
+  const double mag = C.hi * n2 + zz;
+  const double t = __builtin_fma(C.hi, n2, -zz);
+  if (__builtin_fabs(t) > 0x1p-49 * mag) return sgn(z0) * sgn(t);
   dd X = two_prod(x, x), Y = two_prod(y, y), Z = two_prod(z, z);
   double ph, s;
   dd p = two_prod(C.hi, X.hi);
@@ -313,7 +314,7 @@ __host__ __device__ __forceinline__ int height_cmp(double z0, double z, double n
   SPHINT_CDC_STEP(-1.0, Z.lo)
 #undef SPHINT_CDC_STEP
   double w = ph + s;
-  if (__builtin_fabs(w) > 0x1p-92 * (C.hi * nrm * nrm + Z.hi)) return sgn(z0) * sgn(w);
+  if (__builtin_fabs(w) > 0x1p-92 * mag) return sgn(z0) * sgn(w);
   return UNDECIDED;
 }
 
@@ -360,65 +361,106 @@ __host__ __device__ __forceinline__ void points_eft(const ArcEft& a, double z0, 
 
 // ====================================================================== pair drivers
 
-// resolve(need, fn) must run fn() on every caller with need == true (the GPU runs them one
-// lane at a time per wavefront; the CPU build runs them at once).  All callers of one
-// wavefront must reach every resolve call.
-template <class Resolve>
-__host__ __device__ __forceinline__ PairOut eval_eft(bool valid, double x1, double y1, double z1,
-                                                     double x2, double y2, double z2, double z0,
-                                                     double* arena, Resolve&& resolve) {
-  ArcEft A;
-  A.flags = F_NONFINITE;
-  A.d1 = A.d2 = 0;
-  if (valid) arc_eft(x1, y1, z1, x2, y2, z2, A);
-  bool live = valid && A.flags == 0;
-  unsigned extra = 0;
-  auto exact = [&](int which) {
-    int r = exact_sign(which, x1, y1, z1, x2, y2, z2, z0, arena);
-    extra |= F_FALLBACK;
-    if (r == 2) {
-      extra |= F_INTERNAL;
-      r = 0;
+// Exact signs of the five predicates of one pair (exact_sign), for the forced evaluation.
+struct ExactSigns {
+  int d1, d2, s2, h1, h2;  // h_i = sign(z0^2 |x_i|^2 - z_i^2)
+};
+
+__host__ __device__ __forceinline__ ExactSigns exact_signs(double x1, double y1, double z1,
+                                                           double x2, double y2, double z2,
+                                                           double z0, double* arena,
+                                                           bool& overflow) {
+  ExactSigns e;
+  int r[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    r[k] = exact_sign(k, x1, y1, z1, x2, y2, z2, z0, arena);
+    if (r[k] == 2) {
+      overflow = true;
+      r[k] = 0;
     }
-    return r;
-  };
-  resolve(live && (A.d1 == UNDECIDED || A.d2 == UNDECIDED), [&] {
-    if (A.d1 == UNDECIDED) A.d1 = exact(PRED_D1);
-    if (A.d2 == UNDECIDED) A.d2 = exact(PRED_D2);
-  });
+  }
+  e.s2 = r[PRED_S2];
+  e.d1 = r[PRED_D1];
+  e.d2 = r[PRED_D2];
+  e.h1 = r[PRED_H1];
+  e.h2 = r[PRED_H2];
+  return e;
+}
+
+// One pair in EFT mode.  FORCED == false: every decision comes from the floating-point
+// filters; if one cannot decide, the result carries F_NEEDEXACT and nothing else is valid.
+// FORCED == true: the decisions are the exact signs `ex` (the filters are skipped), so the
+// result is final.  Both evaluate the same AccuX arithmetic.
+template <bool FORCED>
+__host__ __device__ __forceinline__ PairOut eval_eft_core(bool valid, double x1, double y1,
+                                                          double z1, double x2, double y2,
+                                                          double z2, double z0,
+                                                          const ExactSigns& ex) {
   PairOut o;
   o.count = 0;
   o.r0 = o.r1 = 0;
   o.px0 = o.py0 = o.px1 = o.py1 = 0.0;
-  o.flags = valid ? A.flags : 0u;
-  if (live && !finite(z0)) {
+  o.flags = 0;
+  if (!valid) return o;
+  ArcEft A;
+  arc_eft(x1, y1, z1, x2, y2, z2, A);
+  if (A.flags) {
+    o.flags = A.flags;
+    return o;
+  }
+  if (!finite(z0)) {
     o.flags = F_NONFINITE;
-    live = false;
+    return o;
   }
-  S2Eft S;
-  S.sign = -1;
-  S.ss = S.ess = 0.0;
-  if (live) S = s2_eft(A, z0);
-  resolve(live && S.sign == UNDECIDED, [&] { S.sign = exact(PRED_S2); });
-  const bool exists = live && S.sign >= 0;
-  int c1 = 0, c2 = 0;
-  if (exists) {
-    dd C = two_prod(z0, z0);
-    c1 = height_cmp(z0, A.z1, A.nrm1, x1, y1, C);
-    c2 = height_cmp(z0, A.z2, A.nrm2, x2, y2, C);
+  const int d1 = FORCED ? ex.d1 : d_sign(A, x1, y1);
+  const int d2 = FORCED ? ex.d2 : d_sign(A, x2, y2);
+  S2Eft S = s2_eft(A, z0);
+  if (FORCED) S.sign = ex.s2;
+  if (!FORCED && (d1 == UNDECIDED || d2 == UNDECIDED || S.sign == UNDECIDED)) {
+    o.flags = F_NEEDEXACT;
+    return o;
   }
-  resolve(exists && (c1 == UNDECIDED || c2 == UNDECIDED), [&] {
-    int sz = sgn(z0);
-    if (c1 == UNDECIDED) c1 = sz * exact(PRED_H1);
-    if (c2 == UNDECIDED) c2 = sz * exact(PRED_H2);
-  });
-  if (exists) {
-    const bool tangent = S.sign == 0;
-    o.flags = F_EXISTS | (tangent ? F_TANGENT : 0u);
-    o.count = hit_rule(A.d1, A.d2, c1, c2, tangent, o.r0, o.r1);
-    if (o.count) points_eft(A, z0, S, o);
+  if (S.sign < 0) return o;
+  const dd C = two_prod(z0, z0);
+  int c1, c2;
+  if (FORCED) {
+    // sign(z0 - z/|x|): decided by the signs of z0 and z, else by sgn(z0) * h
+    c1 = z0 == 0.0 ? -sgn(A.z1) : ((A.z1 == 0.0 || (z0 > 0.0) != (A.z1 > 0.0)) ? sgn(z0) : sgn(z0) * ex.h1);
+    c2 = z0 == 0.0 ? -sgn(A.z2) : ((A.z2 == 0.0 || (z0 > 0.0) != (A.z2 > 0.0)) ? sgn(z0) : sgn(z0) * ex.h2);
+  } else {
+    c1 = height_cmp(z0, A.z1, A.n21, A.zz1, x1, y1, C);
+    c2 = height_cmp(z0, A.z2, A.n22, A.zz2, x2, y2, C);
+    if (c1 == UNDECIDED || c2 == UNDECIDED) {
+      o.flags = F_NEEDEXACT;
+      return o;
+    }
   }
-  o.flags |= extra;
+  const bool tangent = S.sign == 0;
+  o.flags = F_EXISTS | (tangent ? F_TANGENT : 0u) | (FORCED ? F_FALLBACK : 0u);
+  o.count = hit_rule(d1, d2, c1, c2, tangent, o.r0, o.r1);
+  if (o.count) points_eft(A, z0, S, o);
+  return o;
+}
+
+// EFT evaluation with exact decisions.  resolve(need, fn) must run fn() on every caller
+// with need == true (the GPU runs them one lane at a time per wavefront; the CPU build runs
+// them at once); all callers of one wavefront must reach the call.  The fast evaluation
+// runs for every pair; only pairs a filter could not decide get their five exact signs
+// (in the arena) and a forced re-evaluation.
+template <class Resolve>
+__host__ __device__ __forceinline__ PairOut eval_eft(bool valid, double x1, double y1, double z1,
+                                                     double x2, double y2, double z2, double z0,
+                                                     double* arena, Resolve&& resolve) {
+  ExactSigns ex = {0, 0, 0, 0, 0};
+  PairOut o = eval_eft_core<false>(valid, x1, y1, z1, x2, y2, z2, z0, ex);
+  const bool need = (o.flags & F_NEEDEXACT) != 0;
+  bool overflow = false;
+  resolve(need, [&] { ex = exact_signs(x1, y1, z1, x2, y2, z2, z0, arena, overflow); });
+  if (need) {
+    o = eval_eft_core<true>(valid, x1, y1, z1, x2, y2, z2, z0, ex);
+    if (overflow) o.flags |= F_INTERNAL;
+  }
   return o;
 }
 
