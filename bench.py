@@ -13,11 +13,15 @@ Prints one JSON line.  Extra lines go to stderr.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
 
 METRIC = "arc-latitude intersections/s (EFT vs naive FP64, ≤4·2^-53 err); p99 latency"
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
@@ -31,6 +35,40 @@ NAIVE_OPS_PER_PAIR = 38
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest():
+    """sha256 over the kernel sources, the public header and the build flags."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2510_09892_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
+                   if f.endswith((".hip", ".hpp")))
+    files += [os.path.join(ROOT, "include", "sphint.h"),
+              os.path.join(ROOT, "paper_2510_09892_amd", "build.py")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_tag, digest):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of
+    this kernel, or None when the summary is absent or was taken from other sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    got = dict(re.findall(r"^- (\w+): `([^`]+)`", txt, re.M))
+    if got.get("source_sha256") != digest:
+        return None
+    try:
+        return {"fetch_bytes": float(got["fetch_bytes_per_launch"]),
+                "write_bytes": float(got["write_bytes_per_launch"]),
+                "bytes": float(got["fetch_bytes_per_launch"]) + float(got["write_bytes_per_launch"]),
+                "source": os.path.relpath(path, ROOT)}
+    except (KeyError, ValueError):
+        return None
 
 
 def run_mode(torch, sphint, dev, mode, steps, warmup):
@@ -54,6 +92,11 @@ def run_mode(torch, sphint, dev, mode, steps, warmup):
     total2 = out.check()
     assert total2 == total
     return dict(wall_s=t1 - t0, kernel_ms=kms, total=total, out=out)
+
+
+def pctl(v):
+    v = sorted(v)
+    return [v[int(q * (len(v) - 1))] for q in (0.1, 0.5, 0.9)]
 
 
 def latency_small(torch, sphint, inputs, reps=200):
@@ -94,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--modes", default="eft,naive")
-    ap.add_argument("--cpu-sample", type=int, default=450_000)
+    ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -156,9 +199,14 @@ def main():
            "unit": "Tlane-op/s (binary64)", "frac": ops / ALU_PEAK}
     roof = dict(hbm if hbm["frac"] >= alu["frac"] else alu)
     other = alu if roof["bound"] == "hbm" else hbm
-    roof["traffic"] = None
-    roof["kernel"] = f"k_intersect<{1 if head == 'eft' else 0},1>"
+    tag = f"k_intersect_w_{head}_ill1e7"
+    tr = measured_traffic(tag, source_digest())
+    roof["traffic"] = tr["bytes"] if tr else None
+    if tr:
+        roof["traffic_detail"] = tr
+    roof["kernel"] = f"sphint::k_intersect_w<{1 if head == 'eft' else 0},4,false>"
     roof["kernel_ms"] = kms
+    roof["kernel_ms_p10_p50_p90"] = pctl(r["kernel_ms"])
     roof["algorithmic_bytes"] = bytes_launch
     roof["algorithmic_ops"] = ops_launch
     roof["other_bound"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
