@@ -28,9 +28,14 @@ HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 ALU_PEAK = 256 * 64 * 2.4e9  # binary64 lane operations/s: 256 CUs x 64 lanes x 2.4 GHz
 BYTES_PER_PAIR = 7 * 8 + 2   # x1, y1, z1, x2, y2, z2, z0 read; count + flags written
 BYTES_PER_HIT = 8 + 8 + 8 + 1  # x, y, pair, root
-EFT_OPS_PER_PAIR = 254       # algorithmic binary64 operations (arc part 161 + pair part 93)
-EFT_OPS_PER_HIT = 84         # two compensated dot products and two divisions per root
-NAIVE_OPS_PER_PAIR = 38
+# Algorithmic binary64 operations (add, sub, mul, FMA, and each sqrt or division, count 1),
+# counted on the operations the method defines (EFT: Alg. 8 with the normal renormalised,
+# plus the first stage of each exact-decision filter; naive: Eq. 2.2 and its predicates).
+EFT_OPS_PER_PAIR = 146 + 79      # per arc (normal, norms, F pairs, filter inputs) + per pair
+EFT_OPS_PER_HITPAIR = 16         # AccSqrt and the root-independent z0 products
+EFT_OPS_PER_HIT = 100            # two six-term CompDots and two divisions per root
+NAIVE_OPS_PER_PAIR = 25
+NAIVE_OPS_PER_HITPAIR = 15       # sqrt, six products, both roots' sums and divisions
 
 
 def log(*a):
@@ -91,7 +96,8 @@ def run_mode(torch, sphint, dev, mode, steps, warmup):
     timer.close()
     total2 = out.check()
     assert total2 == total
-    return dict(wall_s=t1 - t0, kernel_ms=kms, total=total, out=out)
+    hitpairs = int((out.count > 0).sum().item())  # accounting only, after the timed region
+    return dict(wall_s=t1 - t0, kernel_ms=kms, total=total, hitpairs=hitpairs, out=out)
 
 
 def pctl(v):
@@ -114,6 +120,31 @@ def latency_small(torch, sphint, inputs, reps=200):
             lat.append((time.perf_counter() - t0) * 1e6)
     lat.sort()
     return dict(p50_us=lat[len(lat) // 2], p99_us=lat[int(len(lat) * 0.99) - 1], calls=reps)
+
+
+def serving(torch, args, log):
+    """The serving loop on Poisson arrivals (both modes, same arrivals and payloads)."""
+    from paper_2510_09892_amd import inputs, serve
+    log(f"[bench] serving: building {args.serve_pool} request payloads")
+    pool = serve.request_pool(args.serve_pool)
+    arrivals, _ = inputs.request_stream(rate_hz=args.serve_rate, duration_s=args.serve_seconds,
+                                        seed_tag=4)
+    n = len(arrivals)
+    out = {"workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s "
+                       f"({n} requests); request k uses payload k mod {len(pool)} of a pool drawn "
+                       "from log-uniform 1e3..1e6 arcs x log-uniform 1..1000 latitudes (CSR "
+                       "candidates); 64 GiB device budget; 8 slots",
+           "pool_pairs_mean": sum(p.nnz for p in pool) / len(pool)}
+    for mode in ("eft", "naive"):
+        srv = serve.Server(mode=mode, budget_bytes=64 << 30, slots=8)
+        srv.run(arrivals[:64] * 0.0, lambda i: pool[i % len(pool)])  # warm-up: arenas, code
+        log(f"[bench] serving {mode}: {n} requests")
+        rep = srv.run(arrivals, lambda i: pool[i % len(pool)], check_every=97)
+        srv.close()
+        log(f"[bench] serving {mode}: {rep['req_per_s']:.0f} req/s, p50 {rep['latency_ms']['p50']:.3f} ms, "
+            f"p99 {rep['latency_ms']['p99']:.3f} ms")
+        out[mode] = rep
+    return out
 
 
 def cpu_baseline(P, inputs, sample):
@@ -140,6 +171,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-pool", type=int, default=64)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a torch copy of this many bytes (profiler calibration)")
     args = ap.parse_args()
@@ -188,9 +223,9 @@ def main():
     hits = r["total"]
     bytes_launch = BYTES_PER_PAIR * n + BYTES_PER_HIT * hits
     if head == "eft":
-        ops_launch = EFT_OPS_PER_PAIR * n + EFT_OPS_PER_HIT * hits
+        ops_launch = EFT_OPS_PER_PAIR * n + EFT_OPS_PER_HITPAIR * r["hitpairs"] + EFT_OPS_PER_HIT * hits
     else:
-        ops_launch = NAIVE_OPS_PER_PAIR * n
+        ops_launch = NAIVE_OPS_PER_PAIR * n + NAIVE_OPS_PER_HITPAIR * r["hitpairs"]
     bw = bytes_launch / (kms * 1e-3)
     ops = ops_launch / (kms * 1e-3)
     hbm = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
@@ -239,6 +274,8 @@ def main():
     if not args.no_latency:
         log("[bench] latency, 1e5 uniform arcs")
         line["latency_1e5"] = latency_small(torch, sphint, inputs)
+    if not args.no_serve:
+        line["serving"] = serving(torch, args, log)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

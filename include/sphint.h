@@ -32,6 +32,14 @@
  * allocates on these calls.  Calls are asynchronous on `stream` (a hipStream_t; NULL is the
  * default stream): outputs are valid once the stream reaches the end of the call.  All
  * entry points are reentrant; concurrent calls must use distinct workspaces.
+ *
+ * Ordering across streams: each launch's grid is sized to what the device holds at once and
+ * needs all of its workgroups resident together, so the library orders its launches on one
+ * device across streams (every launch waits, on the device, for the previous launch of the
+ * device, whatever stream that used).  Work of other libraries on other streams still
+ * overlaps.  Launches recorded while a stream is being captured into a graph are not
+ * ordered this way: replays of such graphs on different streams must not overlap.  The
+ * stream must belong to the current device.
  */
 #ifndef SPHINT_H
 #define SPHINT_H
@@ -168,6 +176,11 @@ sphint_status sphint_batch_params(const sphint_plan *plan, int *pairs_per_thread
 /* Sets the schedule by hand (pairs_per_thread 1, 2 or 4; wg_per_cu >= 0, capped at what a CU
  * holds) instead of the autotuner's choice; the next launch re-captures the graph. */
 sphint_status sphint_batch_set_params(sphint_plan *plan, int pairs_per_thread, int wg_per_cu);
+/* After the stream has completed a launch of the plan: SPHINT_E_DEVICE if a kernel of that
+ * launch reported an internal limit (as sphint_check), else SPHINT_E_CAPACITY if some mesh's
+ * *out_total exceeds its out.capacity, else SPHINT_OK.  Synchronous (reads the plan's error
+ * word and every mesh's total). */
+sphint_status sphint_batch_check(const sphint_plan *plan);
 void sphint_plan_destroy(sphint_plan *plan);
 
 const char *sphint_status_string(sphint_status s);

@@ -98,13 +98,15 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
   uint32_t* ws = (uint32_t*)workspace;
   uint64_t* status = (uint64_t*)((char*)workspace + WS_HEADER);
 
+  LaunchChain chain;
+  if (chain.begin(st) != hipSuccess) return SPHINT_E_HIP;
   int64_t init_threads = ntiles > 0 ? ntiles : 1;
   unsigned init_blocks = (unsigned)((init_threads + 255) / 256);
   if (init_blocks > 1024) init_blocks = 1024;
   hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, ws, status, ntiles, out_total,
                      nnz);
   if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
-  if (nnz == 0) return SPHINT_OK;
+  if (nnz == 0) return chain.end() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
 
   KArgs k = make_args(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out, out_count,
                       out_flags, out_total, ws, status, ntiles);
@@ -114,6 +116,7 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
   if (mode == SPHINT_EFT_FP64) e = csr ? launch_main<1, true>(k, st) : launch_main<1, false>(k, st);
   else e = csr ? launch_main<0, true>(k, st) : launch_main<0, false>(k, st);
   if (e == hipSuccess && prof_stop) e = hipEventRecord(prof_stop, st);
+  if (e == hipSuccess) e = chain.end();
   return e == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
 }
 

@@ -1,15 +1,17 @@
 // Batched meshes: many independent CSR (or dense) calls in one persistent launch.
 //
 // The tiles of all meshes form one sequence (mesh 0's tiles, then mesh 1's, ...).  A
-// persistent grid of workgroups takes tiles from one atomic counter; each tile belongs to one
-// mesh and runs exactly the single-call tile routine on that mesh's arguments, with the
-// mesh's own slice of look-back states, so every mesh's outputs equal those of a
-// sphint_arc_constlat call on that mesh alone.  Tiles of one mesh are taken in increasing
-// order, which keeps the look-back's waits on tiles that are already running.
+// persistent grid no larger than what the device holds at once walks that sequence in a
+// static order (compute wavefront c takes tiles c, c + W, ...); each tile belongs to one mesh
+// and runs the single-call tile routine on that mesh's arguments, with the mesh's own slice
+// of tile states, so every mesh's outputs equal those of a sphint_arc_constlat call on that
+// mesh alone.  The scanner wavefront publishes the in-order prefixes of mesh 0's tiles, then
+// mesh 1's, and so on.
 //
-// Schedule parameters: pairs per lane (wavefront tile = 64 * ppt pairs) and the number of resident
-// workgroups per CU; sphint_batch_autotune times the candidates and keeps the fastest.  The
-// init kernel and the persistent kernel are captured once into a HIP graph and replayed.
+// Schedule parameters: pairs per lane (wavefront tile = 64 * ppt pairs) and the number of
+// resident workgroups per CU; sphint_batch_autotune times the candidates and keeps the
+// fastest.  The init kernel and the persistent kernel are captured once into a HIP graph and
+// replayed.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -165,6 +167,8 @@ void launch_batch(const sphint_plan* p, unsigned grid, hipStream_t st) {
 
 // Enqueues init + persistent kernel on st (no graph).
 sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
+  LaunchChain chain;  // no-op while st is being captured
+  if (chain.begin(st) != hipSuccess) return SPHINT_E_HIP;
   uint32_t* ws = (uint32_t*)p->d_ws;
   uint64_t* status = (uint64_t*)((char*)p->d_ws + WS_HEADER);
   const int n = (int)p->meshes.size();
@@ -185,7 +189,8 @@ sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
     else if (p->ppt == 2) eft ? launch_batch<1, 2>(p, (unsigned)grid, st) : launch_batch<0, 2>(p, (unsigned)grid, st);
     else eft ? launch_batch<1, 4>(p, (unsigned)grid, st) : launch_batch<0, 4>(p, (unsigned)grid, st);
   }
-  return hipGetLastError() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
+  if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
+  return chain.end() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
 }
 
 std::string plan_key(const sphint_plan* p) {
@@ -261,7 +266,11 @@ extern "C" sphint_status sphint_batch_launch(sphint_plan* p, void* stream) {
       return SPHINT_E_HIP;
     }
   }
-  return hipGraphLaunch(p->exec, st) == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
+  LaunchChain chain;
+  if (chain.begin(st) != hipSuccess || hipGraphLaunch(p->exec, st) != hipSuccess ||
+      chain.end() != hipSuccess)
+    return SPHINT_E_HIP;
+  return SPHINT_OK;
 }
 
 extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache_path,
@@ -291,8 +300,16 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
       fclose(f);
     }
   }
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SPHINT_E_HIP;
+  struct Events {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } ev;
+  if (hipEventCreate(&ev.e0) != hipSuccess || hipEventCreate(&ev.e1) != hipSuccess)
+    return SPHINT_E_HIP;
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   float best = 1e30f;
   int best_ppt = 1, best_wg = 0;
   const int ppts[3] = {1, 2, 4};
@@ -321,8 +338,6 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   p->ppt = best_ppt;
   p->wg_per_cu = best_wg;
   sphint_status s = layout(p);
@@ -352,6 +367,21 @@ extern "C" sphint_status sphint_batch_set_params(sphint_plan* p, int pairs_per_t
   p->ppt = pairs_per_thread;
   p->wg_per_cu = wg_per_cu;
   return layout(p);
+}
+
+extern "C" sphint_status sphint_batch_check(const sphint_plan* p) {
+  if (!p || !p->d_ws) return SPHINT_E_INVAL;
+  uint32_t hdr[2] = {0, 0};
+  if (hipMemcpy(hdr, p->d_ws, sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess)
+    return SPHINT_E_HIP;
+  if (hdr[1]) return SPHINT_E_DEVICE;
+  for (const auto& m : p->meshes) {
+    int64_t t = 0;
+    if (hipMemcpy(&t, m.out_total, sizeof(t), hipMemcpyDeviceToHost) != hipSuccess)
+      return SPHINT_E_HIP;
+    if (t > m.out.capacity) return SPHINT_E_CAPACITY;
+  }
+  return SPHINT_OK;
 }
 
 extern "C" void sphint_plan_destroy(sphint_plan* p) {

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "sphint.h"
 #include "sphint_kernels.hpp"
 
@@ -66,5 +68,75 @@ inline KArgs make_args(int64_t n_arcs, const sphint_pts_soa& p1, const sphint_pt
   k.ntiles = ntiles;
   return k;
 }
+
+// Cross-stream ordering of this library's launches on one device.  A persistent grid is
+// sized to what the device holds at once and relies on all its workgroups being resident
+// together (every wait inside a launch is on a tile of a running wavefront).  Two such
+// launches running at once on different streams could each hold part of the device and
+// wait for workgroups that the other keeps out, until the bounded waits give up.  So each
+// launch waits for the previous launch of the device, on whatever stream that one ran (one
+// event per device).  Launches being captured into a graph are not chained: a caller that
+// replays graphs on several streams orders the replays itself.  The stream must belong to
+// the current device.
+struct ChainState {
+  std::mutex m;
+  hipEvent_t ev = nullptr;
+  hipStream_t last = nullptr;
+  bool armed = false;
+};
+
+inline ChainState& chain_state(int dev) {
+  static ChainState s[64];
+  return s[dev & 63];
+}
+
+class LaunchChain {
+ public:
+  LaunchChain() = default;
+  LaunchChain(const LaunchChain&) = delete;
+  LaunchChain& operator=(const LaunchChain&) = delete;
+  ~LaunchChain() {
+    if (c_) c_->m.unlock();
+  }
+
+  // Call before the launch: makes `st` wait for the device's previous launch.
+  hipError_t begin(hipStream_t st) {
+    st_ = st;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    ChainState& c = chain_state(dev);
+    c.m.lock();
+    c_ = &c;
+    if (!c.ev) {
+      e = hipEventCreateWithFlags(&c.ev, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        c.ev = nullptr;
+        return e;
+      }
+    }
+    if (c.armed && c.last != st) return hipStreamWaitEvent(st, c.ev, 0);
+    return hipSuccess;
+  }
+
+  // Call after the launch was enqueued: the next launch of the device waits for this one.
+  hipError_t end() {
+    if (!c_) return hipSuccess;
+    hipError_t e = hipEventRecord(c_->ev, st_);
+    if (e == hipSuccess) {
+      c_->armed = true;
+      c_->last = st_;
+    }
+    return e;
+  }
+
+ private:
+  ChainState* c_ = nullptr;
+  hipStream_t st_ = nullptr;
+};
 
 }  // namespace sphint

@@ -1,12 +1,15 @@
 // gfx950 kernels for the arc x constant-latitude intersection (Sec. 2, Eq. 2.2; Alg. 8).
 //
-// One lane per arc-latitude pair, 256-lane workgroups (four wave64s).  Each workgroup takes
-// a tile of consecutive pairs, evaluates them (naive or EFT), then writes its hits into one
-// dense output in pair order: a ballot/popcount scan inside each wavefront, a four-entry
-// scan across wavefronts, and a single-pass decoupled look-back across tiles (tile ids are
-// taken from an atomic counter in start order, so every tile waited on is already
-// running).  Rare undecided exact predicates are resolved one lane at a time per wavefront
-// in an LDS arena (exact_sign), keeping private arrays and scratch out of the kernel.
+// One lane per arc-latitude pair.  A wavefront owns tiles of 64 * WPPT consecutive pairs
+// (row j of a tile is pairs base + 64 j + lane) and evaluates them (naive or EFT), writing
+// per-pair counts and flags at once.  Hits go into one dense output in pair order: a
+// ballot/popcount scan inside the wavefront gives in-tile offsets, the wavefront publishes
+// its tile's hit count, and one scanner wavefront per launch turns the counts into
+// exclusive prefixes in tile order.  The grid is persistent and never larger than what the
+// device holds at once, with a static tile order, so every tile the scanner waits for
+// belongs to a running wavefront.  Hits wait in LDS until their tile's prefix is known and
+// are then copied out in contiguous runs.  Rare undecided exact predicates are resolved one
+// lane at a time per wavefront in an LDS arena (exact_sign).
 #pragma once
 #pragma clang fp contract(off)
 

@@ -25,7 +25,8 @@ ROOT_PLUS, ROOT_MINUS = 0, 1
 EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_set_profile_events",
            "sphint_batch_plan_create", "sphint_batch_autotune", "sphint_batch_launch",
-           "sphint_batch_params", "sphint_batch_set_params", "sphint_plan_destroy",
+           "sphint_batch_params", "sphint_batch_set_params", "sphint_batch_check",
+           "sphint_plan_destroy",
            "sphint_status_string",
            "sphint_version")
 
@@ -84,6 +85,8 @@ def load():
     lib.sphint_batch_params.restype = ctypes.c_int
     lib.sphint_batch_set_params.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.sphint_batch_set_params.restype = ctypes.c_int
+    lib.sphint_batch_check.argtypes = [vp]
+    lib.sphint_batch_check.restype = ctypes.c_int
     lib.sphint_plan_destroy.argtypes = [vp]
     lib.sphint_plan_destroy.restype = None
     lib.sphint_status_string.argtypes = [ctypes.c_int]
@@ -195,6 +198,28 @@ def arc_constlat(p1, p2, lat_z, lat_offsets=None, lat_idx=None, mode="eft", out=
     return out
 
 
+def arc_constlat_raw(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, hits, count,
+                     flags, total, mode, workspace, workspace_bytes, stream):
+    """sphint_arc_constlat on raw device addresses (ints; 0 for NULL), for callers that manage
+    their own device memory.  ``p1``/``p2`` are (x, y, z) address triples, ``hits`` is
+    (x, y, pair, root, capacity), ``stream`` a hipStream_t value.  Nothing is synchronised."""
+    st = load().sphint_arc_constlat(
+        n_arcs, PtsSoA(*p1), PtsSoA(*p2), lat_z or None, n_lat, lat_offsets or None,
+        lat_idx or None, nnz, Hits(*hits), count or None, flags or None, total, MODES[mode],
+        workspace, workspace_bytes, ctypes.c_void_p(stream))
+    _check(st, "sphint_arc_constlat")
+
+
+def workspace_size(nnz):
+    """sphint_workspace_size: workspace bytes for a call over nnz pairs."""
+    return int(load().sphint_workspace_size(nnz))
+
+
+def check_raw(workspace, host_total, capacity):
+    """sphint_check on a raw workspace address (synchronous)."""
+    _check(load().sphint_check(ctypes.c_void_p(workspace), host_total, capacity), "sphint_check")
+
+
 class KernelTimer:
     """HIP events the library records around its main kernel (sphint_set_profile_events).
 
@@ -283,6 +308,11 @@ class BatchPlan:
     def set_params(self, pairs_per_thread, wg_per_cu):
         _check(load().sphint_batch_set_params(self.handle, pairs_per_thread, wg_per_cu),
                "sphint_batch_set_params")
+
+    def check(self):
+        """Synchronises; raises if a kernel of the last launch reported an internal limit or
+        a mesh's hits overflowed its capacity."""
+        _check(load().sphint_batch_check(self.handle), "sphint_batch_check")
 
     def close(self):
         if self.handle:

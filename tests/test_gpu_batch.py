@@ -1,0 +1,155 @@
+"""GPU: the batched persistent launch (sphint_batch_*) over many uneven meshes.
+
+* One graph-replayed launch over all meshes gives, for every mesh, the bytes of a
+  per-mesh sphint_arc_constlat call (counts, flags, hits), in both modes.
+* Every tile/schedule parameter choice the autotuner may pick gives the same bytes.
+* Graph replays, with eager work and synchronisations between them, all give the same
+  bytes; the autotuner's cache file is written and read back.
+* One small mesh against the oracle.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import batch as OB
+from paper_2510_09892_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FLAG_MASK = 31
+
+
+def note(msg):
+    print(f"[gpu-batch] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+def make_meshes(n=7, seed_tag=40):
+    g = inputs.rng(seed_tag)
+    out = []
+    for k in range(n):
+        arcs = int(np.exp(g.uniform(np.log(200), np.log(60_000))))
+        lats = int(g.integers(10, 900))
+        out.append(inputs.random_mesh(inputs.rng(seed_tag, k + 1), arcs, lats))
+    return out
+
+
+def to_dev(torch, m):
+    from paper_2510_09892_amd import sphint
+    d = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in m.soa()]
+    return dict(p1=tuple(d[:3]), p2=tuple(d[3:]), lat_z=torch.from_numpy(m.lat_z).cuda(),
+                lat_offsets=torch.from_numpy(m.lat_offsets).cuda(),
+                lat_idx=torch.from_numpy(m.lat_idx).cuda(), out=sphint.Output(m.nnz))
+
+
+def read(out):
+    t = int(out.total.item())
+    return dict(total=t, count=out.count.cpu().numpy().copy(), flags=out.flags.cpu().numpy().copy(),
+                x=out.x[:t].cpu().numpy().copy(), y=out.y[:t].cpu().numpy().copy(),
+                pair=out.pair[:t].cpu().numpy().copy(), root=out.root[:t].cpu().numpy().copy())
+
+
+def same(a, b):
+    return a["total"] == b["total"] and all(
+        np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8))
+        for k in ("count", "flags", "x", "y", "pair", "root"))
+
+
+def per_mesh(torch, devs, mode):
+    from paper_2510_09892_amd import sphint
+    res = []
+    for d in devs:
+        o = sphint.Output(d["out"].nnz)
+        sphint.arc_constlat(d["p1"], d["p2"], d["lat_z"], d["lat_offsets"], d["lat_idx"],
+                            mode=mode, out=o)
+        torch.cuda.synchronize()
+        o.check()
+        res.append(read(o))
+    return res
+
+
+def scrub(torch, devs):
+    for d in devs:
+        o = d["out"]
+        for t in (o.x, o.y):
+            t.fill_(float("nan"))
+        o.pair.fill_(-1)
+        o.root.fill_(255)
+        o.count.fill_(255)
+        o.flags.fill_(255)
+        o.total.fill_(-1)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode", ["eft", "naive"])
+def test_batch_equals_per_mesh(torch_cuda, mode, tmp_path):
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    meshes = make_meshes()
+    note(f"{mode}: {len(meshes)} meshes, nnz {[m.nnz for m in meshes]}")
+    devs = [to_dev(torch, m) for m in meshes]
+    ref = per_mesh(torch, devs, mode)
+    plan = sphint.BatchPlan(devs, mode=mode)
+    try:
+        for ppt in (1, 2, 4):
+            for wg in (0, 1, 2):
+                note(f"{mode}: params ppt={ppt} wg_per_cu={wg}")
+                plan.set_params(ppt, wg)
+                scrub(torch, devs)
+                plan.launch()
+                torch.cuda.synchronize()
+                plan.check()
+                for d, r in zip(devs, ref):
+                    assert same(read(d["out"]), r), (ppt, wg)
+        cache = os.path.join(str(tmp_path), "tune.txt")
+        note(f"{mode}: autotune")
+        plan.autotune(cache)
+        chosen = plan.params()
+        assert chosen[0] in (1, 2, 4) and chosen[1] >= 0
+        assert os.path.exists(cache) and open(cache).read().strip()
+        plan.set_params(1, 1)
+        plan.autotune(cache)  # read back from the cache
+        assert plan.params() == chosen
+        for rep in range(4):  # graph replays with eager work in between
+            note(f"{mode}: replay {rep}")
+            scrub(torch, devs)
+            eager = torch.arange(1000, device="cuda", dtype=torch.float64).sum()
+            plan.launch()
+            torch.cuda.synchronize()
+            assert float(eager.item()) == 499500.0
+            plan.check()
+            for d, r in zip(devs, ref):
+                assert same(read(d["out"]), r), rep
+    finally:
+        plan.close()
+
+
+def test_batch_small_mesh_against_oracle(torch_cuda):
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    meshes = [inputs.random_mesh(inputs.rng(41, k), 400 + 300 * k, 60 + 40 * k) for k in range(3)]
+    devs = [to_dev(torch, m) for m in meshes]
+    plan = sphint.BatchPlan(devs, mode="eft")
+    try:
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.check()
+        for m, d in zip(meshes, devs):
+            r = read(d["out"])
+            ex = OB.exact(*m.expand().soa(), workers=1)
+            np.testing.assert_array_equal(r["count"], ex.count)
+            np.testing.assert_array_equal(r["flags"] & FLAG_MASK, ex.flags)
+            np.testing.assert_array_equal(r["pair"], np.array(ex.hit_pair, dtype=np.int64))
+    finally:
+        plan.close()

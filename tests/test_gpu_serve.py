@@ -1,0 +1,124 @@
+"""GPU: the serving loop and launches from several streams.
+
+* Every request's outputs in a served mix (several slots in flight, admission held back
+  by a small device-memory budget) are bit-identical to the same request run alone.
+* Launches on different streams at once give the results of the same launches run one
+  after the other (the library orders its launches on the device).
+* A few served requests are checked against the oracle.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import batch as OB
+from paper_2510_09892_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FLAG_MASK = 31
+KEYS = ("count", "flags", "x", "y", "pair", "root")
+
+
+def note(msg):
+    print(f"[gpu-serve] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+def alone(torch, mesh, mode):
+    from paper_2510_09892_amd import sphint
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in mesh.soa()]
+    lz, off, idx = (torch.from_numpy(a).cuda() for a in (mesh.lat_z, mesh.lat_offsets, mesh.lat_idx))
+    out = sphint.Output(mesh.nnz)
+    sphint.arc_constlat(tuple(dev[:3]), tuple(dev[3:]), lz, off, idx, mode=mode, out=out)
+    torch.cuda.synchronize()
+    t = out.check()
+    return dict(total=t, count=out.count.cpu().numpy(), flags=out.flags.cpu().numpy(),
+                x=out.x[:t].cpu().numpy(), y=out.y[:t].cpu().numpy(),
+                pair=out.pair[:t].cpu().numpy(), root=out.root[:t].cpu().numpy())
+
+
+def same_bytes(a, b):
+    return all(np.array_equal(np.asarray(a[k]).view(np.uint8), np.asarray(b[k]).view(np.uint8))
+               for k in KEYS) and a["total"] == b["total"]
+
+
+@pytest.mark.parametrize("mode", ["eft", "naive"])
+def test_served_mix_equals_alone(torch_cuda, mode):
+    from paper_2510_09892_amd import serve
+    torch = torch_cuda
+    note(f"building request pool ({mode})")
+    meshes = []
+    g = inputs.rng(31)
+    pool = []
+    for k in range(10):
+        m = inputs.random_mesh(inputs.rng(31, k + 1), int(g.integers(500, 30_000)),
+                               int(g.integers(1, 400)))
+        meshes.append(m)
+        pool.append(serve.Payload(m))
+    n_req = 60
+    arrivals = np.sort(inputs.rng(32).uniform(0.0, 0.004, n_req))  # a burst: requests pile up
+    which = [int(v) for v in inputs.rng(33).integers(0, len(pool), n_req)]
+    budget = 3 * max(p.footprint for p in pool)
+    srv = serve.Server(mode=mode, budget_bytes=budget, slots=4)
+    note(f"serving {n_req} requests, budget {budget} bytes, 4 slots")
+    rep, outs = srv.run(arrivals, lambda i: pool[which[i]], keep_outputs=True)
+    srv.close()
+    note(f"served: {rep['req_per_s']:.0f} req/s, max in flight {rep['max_inflight']}, "
+         f"budget waits {rep['admission_waits_on_budget']}")
+    assert rep["requests"] == n_req and len(outs) == n_req
+    assert rep["max_inflight"] > 1
+    assert rep["admission_waits_on_budget"] > 0
+    ref = {}
+    for rid in range(n_req):
+        k = which[rid]
+        if k not in ref:
+            ref[k] = alone(torch, meshes[k], mode)
+        assert same_bytes(outs[rid], ref[k]), (rid, k)
+    # two served requests against the oracle
+    for k in sorted(ref, key=lambda k: meshes[k].nnz)[:2]:
+        soa = meshes[k].expand().soa()
+        r = ref[k]
+        if mode == "eft":
+            ex = OB.exact(*soa, workers=1)
+            np.testing.assert_array_equal(r["count"], ex.count)
+            np.testing.assert_array_equal(r["flags"] & FLAG_MASK, ex.flags)
+        else:
+            nv = OB.naive_fp64(*soa, workers=1)
+            np.testing.assert_array_equal(r["count"], nv.count)
+            np.testing.assert_array_equal(r["x"], np.array(nv.hit_x))
+
+
+def test_concurrent_streams_equal_serial(torch_cuda):
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    P = [inputs.ill_conditioned(600_000, seed_tag=34 + k) for k in range(3)]
+    dev = [[torch.from_numpy(a).cuda() for a in p.soa()] for p in P]
+    note("serial launches")
+    serial = []
+    for d in dev:
+        out = sphint.Output(len(d[6]))
+        sphint.arc_constlat(tuple(d[:3]), tuple(d[3:6]), d[6], mode="eft", out=out)
+        torch.cuda.synchronize()
+        t = out.check()
+        serial.append((t, out.count.cpu().numpy(), out.x[:t].cpu().numpy()))
+    note("concurrent launches on three streams, four rounds")
+    streams = [torch.cuda.Stream() for _ in dev]
+    outs = [sphint.Output(len(d[6])) for d in dev]
+    for _ in range(4):
+        for d, s, o in zip(dev, streams, outs):
+            sphint.arc_constlat(tuple(d[:3]), tuple(d[3:6]), d[6], mode="eft", out=o, stream=s)
+    torch.cuda.synchronize()
+    for (t, c, x), o in zip(serial, outs):
+        assert o.check() == t
+        assert np.array_equal(o.count.cpu().numpy(), c)
+        assert np.array_equal(o.x[:t].cpu().numpy().view(np.uint8), x.view(np.uint8))
