@@ -76,19 +76,18 @@ def measured_traffic(kernel_tag, digest):
         return None
 
 
-def run_mode(torch, sphint, dev, mode, steps, warmup):
-    x1, y1, z1, x2, y2, z2, z0 = dev
-    n = len(z0)
-    out = sphint.Output(n)
+def run_mode(torch, sphint, call, nnz, mode, steps, warmup):
+    """Times `steps` calls of call(out, mode) (one sphint_arc_constlat each)."""
+    out = sphint.Output(nnz)
     for _ in range(warmup):
-        sphint.arc_constlat((x1, y1, z1), (x2, y2, z2), z0, mode=mode, out=out)
+        call(out, mode)
     total = out.check()
     timer = sphint.KernelTimer(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         timer.arm(k)
-        sphint.arc_constlat((x1, y1, z1), (x2, y2, z2), z0, mode=mode, out=out)
+        call(out, mode)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timer.disarm()
@@ -98,6 +97,35 @@ def run_mode(torch, sphint, dev, mode, steps, warmup):
     assert total2 == total
     hitpairs = int((out.count > 0).sum().item())  # accounting only, after the timed region
     return dict(wall_s=t1 - t0, kernel_ms=kms, total=total, hitpairs=hitpairs, out=out)
+
+
+def roofline(mode, r, pairs, bytes_launch, kernel, tag):
+    """Binding roof of the dominant kernel from its mean duration (HIP events)."""
+    kms = statistics.mean(r["kernel_ms"])
+    hits = r["total"]
+    if mode == "eft":
+        ops_launch = EFT_OPS_PER_PAIR * pairs + EFT_OPS_PER_HITPAIR * r["hitpairs"] + EFT_OPS_PER_HIT * hits
+    else:
+        ops_launch = NAIVE_OPS_PER_PAIR * pairs + NAIVE_OPS_PER_HITPAIR * r["hitpairs"]
+    bw = bytes_launch / (kms * 1e-3)
+    ops = ops_launch / (kms * 1e-3)
+    hbm = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+           "frac": bw / HBM_PEAK}
+    alu = {"bound": "alu", "achieved": ops / 1e12, "peak": ALU_PEAK / 1e12,
+           "unit": "Tlane-op/s (binary64)", "frac": ops / ALU_PEAK}
+    roof = dict(hbm if hbm["frac"] >= alu["frac"] else alu)
+    other = alu if roof["bound"] == "hbm" else hbm
+    tr = measured_traffic(tag, source_digest()) if tag else None
+    roof["traffic"] = tr["bytes"] if tr else None
+    if tr:
+        roof["traffic_detail"] = tr
+    roof["kernel"] = kernel
+    roof["kernel_ms"] = kms
+    roof["kernel_ms_p10_p50_p90"] = pctl(r["kernel_ms"])
+    roof["algorithmic_bytes"] = bytes_launch
+    roof["algorithmic_ops"] = ops_launch
+    roof["other_bound"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    return roof
 
 
 def pctl(v):
@@ -161,12 +189,41 @@ def cpu_baseline(P, inputs, sample):
                       f"(exact integer predicates + 100-digit decimal points), {dt:.1f} s wall"}
 
 
+def cpu_baseline_csr(meshes, inputs, sample):
+    """The oracle on `sample` candidate pairs drawn uniformly from the meshes' CSR lists."""
+    import numpy as np
+    from oracle import batch as OB
+    g = np.random.Generator(np.random.PCG64(12))
+    nnz = np.array([m.nnz for m in meshes], dtype=np.float64)
+    which = g.choice(len(meshes), size=sample, p=nnz / nnz.sum())
+    rows = []
+    for k in np.unique(which):
+        m = meshes[k]
+        ks = np.sort(g.choice(m.nnz, size=int((which == k).sum()), replace=m.nnz < (which == k).sum()))
+        arc = np.searchsorted(m.lat_offsets, ks, side="right") - 1
+        rows.append((m.p1[arc], m.p2[arc], m.lat_z[m.lat_idx[ks]]))
+    p1 = np.concatenate([r[0] for r in rows])
+    p2 = np.concatenate([r[1] for r in rows])
+    z0 = np.concatenate([r[2] for r in rows])
+    S = inputs.Pairs(p1, p2, z0)
+    workers = OB.default_workers()
+    t0 = time.perf_counter()
+    OB.exact(*S.soa(), workers=workers)
+    dt = time.perf_counter() - t0
+    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(S)} candidate pairs drawn uniformly from the workload's CSR lists "
+                      f"(exact integer predicates + 100-digit decimal points), {dt:.1f} s wall"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--workload", default="ill1e7", choices=["ill1e7", "cubed1024", "batch64"],
+                    help="ill1e7: the headline (1e7 ill-conditioned dense pairs); cubed1024: "
+                         "regridding-shaped CSR; batch64: 64 uneven meshes in one launch")
     ap.add_argument("--modes", default="eft,naive")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -188,21 +245,53 @@ def main():
     from paper_2510_09892_amd import inputs, sphint
 
     sphint.load()
-    log(f"[bench] generating {args.n} ill-conditioned arcs")
-    P = inputs.ill_conditioned(args.n, seed_tag=1)
+    if args.workload == "batch64":
+        return bench_batch(args, torch, np, inputs, sphint)
+    if args.workload == "cubed1024":
+        log("[bench] generating the ne=1024 cubed sphere x 1800 latitudes")
+        mesh = inputs.cubed_sphere(1024)
+        n = mesh.nnz
+        P = None
+        workload = ("cubed sphere ne=1024: 12,582,912 unique great-circle edges x 1800 latitude "
+                    "lines (-89.95 deg + 0.1 deg k), CSR candidates from z-range overlap, mode ")
+    else:
+        log(f"[bench] generating {args.n} ill-conditioned arcs")
+        P = inputs.ill_conditioned(args.n, seed_tag=1)
+        n = args.n
+        workload = ("1e7 ill-conditioned arcs in three parts (short 1e-10..1e-6 rad; "
+                    "near-tangent r<=1e-12; within 1e-6 rad of a pole), one latitude "
+                    "per arc, dense 1:1, mode ")
     cpu = None
     if not args.no_cpu_baseline:
         # before any GPU call: the oracle's worker processes are forked from this one
         log(f"[bench] cpu baseline: oracle on {args.cpu_sample} pairs")
-        cpu = cpu_baseline(P, inputs, args.cpu_sample)
+        if P is not None:
+            cpu = cpu_baseline(P, inputs, args.cpu_sample)
+        else:
+            cpu = cpu_baseline_csr([mesh], inputs, args.cpu_sample)
         log(f"[bench] cpu baseline {cpu['value']:.0f} pairs/s on {cpu['cores']} workers")
-    dev = [torch.from_numpy(a).cuda() for a in P.soa()]
+    if P is not None:
+        dev = [torch.from_numpy(a).cuda() for a in P.soa()]
+
+        def call(out, mode):
+            sphint.arc_constlat(tuple(dev[:3]), tuple(dev[3:6]), dev[6], mode=mode, out=out)
+        bytes_in = BYTES_PER_PAIR * n
+        csr = False
+    else:
+        dp = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in mesh.soa()]
+        lz, off, idx = (torch.from_numpy(a).cuda() for a in (mesh.lat_z, mesh.lat_offsets, mesh.lat_idx))
+
+        def call(out, mode):
+            sphint.arc_constlat(tuple(dp[:3]), tuple(dp[3:]), lz, off, idx, mode=mode, out=out)
+        # every input array once (endpoints, offsets, indices, latitudes) + counts and flags
+        bytes_in = 48 * mesh.n_arcs + 8 * (mesh.n_arcs + 1) + 4 * n + 8 * len(mesh.lat_z) + 2 * n
+        csr = True
     torch.cuda.synchronize()
 
     res = {}
     for mode in args.modes.split(","):
         log(f"[bench] mode={mode} warmup={args.warmup} steps={args.steps}")
-        res[mode] = run_mode(torch, sphint, dev, mode, args.steps, args.warmup)
+        res[mode] = run_mode(torch, sphint, call, n, mode, args.steps, args.warmup)
         r = res[mode]
         log(f"[bench] mode={mode} wall={r['wall_s']:.4f}s kernel_mean={statistics.mean(r['kernel_ms']):.4f}ms "
             f"hits={r['total']}")
@@ -215,36 +304,13 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {args.copy_calibration} bytes x3")
 
-    n = args.n
     head = "eft" if "eft" in res else next(iter(res))
     r = res[head]
     value = n * args.steps / r["wall_s"]
-    kms = statistics.mean(r["kernel_ms"])
     hits = r["total"]
-    bytes_launch = BYTES_PER_PAIR * n + BYTES_PER_HIT * hits
-    if head == "eft":
-        ops_launch = EFT_OPS_PER_PAIR * n + EFT_OPS_PER_HITPAIR * r["hitpairs"] + EFT_OPS_PER_HIT * hits
-    else:
-        ops_launch = NAIVE_OPS_PER_PAIR * n + NAIVE_OPS_PER_HITPAIR * r["hitpairs"]
-    bw = bytes_launch / (kms * 1e-3)
-    ops = ops_launch / (kms * 1e-3)
-    hbm = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-           "frac": bw / HBM_PEAK}
-    alu = {"bound": "alu", "achieved": ops / 1e12, "peak": ALU_PEAK / 1e12,
-           "unit": "Tlane-op/s (binary64)", "frac": ops / ALU_PEAK}
-    roof = dict(hbm if hbm["frac"] >= alu["frac"] else alu)
-    other = alu if roof["bound"] == "hbm" else hbm
-    tag = f"k_intersect_w_{head}_ill1e7"
-    tr = measured_traffic(tag, source_digest())
-    roof["traffic"] = tr["bytes"] if tr else None
-    if tr:
-        roof["traffic_detail"] = tr
-    roof["kernel"] = f"sphint::k_intersect_w<{1 if head == 'eft' else 0},4,false>"
-    roof["kernel_ms"] = kms
-    roof["kernel_ms_p10_p50_p90"] = pctl(r["kernel_ms"])
-    roof["algorithmic_bytes"] = bytes_launch
-    roof["algorithmic_ops"] = ops_launch
-    roof["other_bound"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    kernel = f"sphint::k_intersect_w<{1 if head == 'eft' else 0},4,{'true' if csr else 'false'}>"
+    tag = f"k_intersect_w_{head}_{args.workload}"
+    roof = roofline(head, r, n, bytes_in + BYTES_PER_HIT * hits, kernel, tag)
 
     line = {
         "metric": METRIC,
@@ -259,23 +325,95 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "1e7 ill-conditioned arcs in three parts (short 1e-10..1e-6 rad; "
-                               "near-tangent r<=1e-12; within 1e-6 rad of a pole), one latitude "
-                               "per arc, dense 1:1, mode " + head,
-                   "pairs": n, "hits": hits},
+        "config": {"workload": workload + head, "pairs": n, "hits": hits},
         "roofline": roof,
     }
     if "naive" in res and head != "naive":
         rn = res["naive"]
         nv = n * args.steps / rn["wall_s"]
         line["naive"] = {"value": nv, "ms_per_step": rn["wall_s"] / args.steps * 1e3,
-                         "kernel_ms": statistics.mean(rn["kernel_ms"]), "hits": rn["total"]}
+                         "kernel_ms": statistics.mean(rn["kernel_ms"]), "hits": rn["total"],
+                         "roofline": roofline("naive", rn, n, bytes_in + BYTES_PER_HIT * rn["total"],
+                                              kernel.replace("<1,", "<0,"),
+                                              f"k_intersect_w_naive_{args.workload}")}
         line["eft_over_naive"] = value / nv
-    if not args.no_latency:
+    if not args.no_latency and args.workload == "ill1e7":
         log("[bench] latency, 1e5 uniform arcs")
         line["latency_1e5"] = latency_small(torch, sphint, inputs)
-    if not args.no_serve:
+    if not args.no_serve and args.workload == "ill1e7":
         line["serving"] = serving(torch, args, log)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args, torch, np, inputs, sphint):
+    """64 uneven meshes: one autotuned persistent graph launch vs 64 per-mesh launches."""
+    g = inputs.rng(3)
+    sizes = np.floor(np.exp(g.uniform(np.log(1e3), np.log(1e7), 64))).astype(int)
+    lats = g.integers(10, 3601, 64)
+    meshes = []
+    for m, (sz, L) in enumerate(zip(sizes, lats)):
+        meshes.append(inputs.random_mesh(inputs.rng(3, 1 + m), int(sz), int(L)))
+        log(f"[bench] mesh {m}: {sz} arcs x {L} latitudes, nnz {meshes[-1].nnz}")
+    nnz = sum(m.nnz for m in meshes)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_csr(meshes, inputs, args.cpu_sample)
+        log(f"[bench] cpu baseline {cpu['value']:.0f} pairs/s on {cpu['cores']} workers")
+    devs = []
+    for m in meshes:
+        d = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in m.soa()]
+        devs.append(dict(p1=tuple(d[:3]), p2=tuple(d[3:]), lat_z=torch.from_numpy(m.lat_z).cuda(),
+                         lat_offsets=torch.from_numpy(m.lat_offsets).cuda(),
+                         lat_idx=torch.from_numpy(m.lat_idx).cuda(), out=sphint.Output(m.nnz)))
+    log(f"[bench] batch: 64 meshes, {sum(m.n_arcs for m in meshes)} arcs, {nnz} pairs on the device")
+    res = {}
+    for mode in args.modes.split(","):
+        def per_mesh():
+            for d in devs:
+                sphint.arc_constlat(d["p1"], d["p2"], d["lat_z"], d["lat_offsets"], d["lat_idx"],
+                                    mode=mode, out=d["out"])
+        for _ in range(args.warmup):
+            per_mesh()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            per_mesh()
+        torch.cuda.synchronize()
+        t_per = (time.perf_counter() - t0) / args.steps
+        plan = sphint.BatchPlan(devs, mode=mode)
+        t1 = time.perf_counter()
+        plan.autotune()
+        t_tune = time.perf_counter() - t1
+        for _ in range(args.warmup):
+            plan.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.launch()
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / args.steps
+        plan.check()
+        hits = sum(int(d["out"].total.item()) for d in devs)
+        res[mode] = dict(ms_per_step=t_batch * 1e3, per_mesh_ms=t_per * 1e3,
+                         speedup_vs_per_mesh=t_per / t_batch, params=plan.params(),
+                         autotune_s=t_tune, hits=hits, value=nnz / t_batch)
+        plan.close()
+        log(f"[bench] batch {mode}: {t_batch * 1e3:.2f} ms (per-mesh launches {t_per * 1e3:.2f} ms), "
+            f"params {res[mode]['params']}")
+    head = "eft" if "eft" in res else next(iter(res))
+    r = res[head]
+    line = {
+        "metric": METRIC, "value": r["value"], "unit": "intersections/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "64 meshes, log-uniform 1e3..1e7 arcs (d <= 0.05 rad) x 10..3600 "
+                               "latitudes, CSR; one autotuned persistent hipGraph launch, mode " + head,
+                   "pairs": nnz, "hits": r["hits"]},
+        "batch": res,
+    }
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
