@@ -97,8 +97,10 @@ typedef struct {
  *   CSR form    pair k is (arc i, latitude lat_z[lat_idx[k]]) for k in
  *               [lat_offsets[i], lat_offsets[i+1]); lat_offsets has n_arcs + 1
  *               non-decreasing entries with lat_offsets[0] == 0 and lat_offsets[n_arcs] ==
- *               nnz; lat_idx has nnz entries in [0, n_lat).  An out-of-range lat_idx entry
- *               yields a NONFINITE pair, not a memory access out of bounds.
+ *               nnz; lat_idx has nnz entries in [0, n_lat); n_arcs < 2^32.  An
+ *               out-of-range lat_idx entry yields a NONFINITE pair, not a memory access
+ *               out of bounds; malformed offsets give unspecified pairs but never an
+ *               access outside the arrays.
  * p1, p2      arc endpoints, n_arcs entries per component (device).
  * out         compacted hits (device); may have capacity 0 with NULL pointers.
  * out_count   [nnz] hit count per pair, 0..2 (device, required when nnz > 0).
@@ -107,7 +109,7 @@ typedef struct {
  * workspace   device memory of at least sphint_workspace_size(nnz) bytes, 256-byte
  *             aligned, used only by this call while it runs.
  * Returns SPHINT_E_INVAL (no launch) for negative sizes, missing pointers, mismatched
- * dense sizes or a short workspace; SPHINT_E_HIP if a launch fails; else SPHINT_OK.
+ * dense sizes, n_arcs >= 2^32 in the CSR form or a short workspace; SPHINT_E_HIP if a launch fails; else SPHINT_OK.
  */
 sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1, sphint_pts_soa p2,
                                   const double *lat_z, int64_t n_lat,
@@ -116,7 +118,9 @@ sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1, sphint_pts_
                                   uint8_t *out_flags, int64_t *out_total, sphint_mode mode,
                                   void *workspace, size_t workspace_bytes, void *stream);
 
-/* Workspace bytes sphint_arc_constlat needs for `nnz` pairs (any mode or form). */
+/* Workspace bytes sphint_arc_constlat needs for `nnz` pairs (any mode or form):
+ * 256 + 8 * max(1, ceil(nnz / 64)) + 4 * nnz (a header, one scan state per tile of the
+ * finest schedule, and the CSR pair-to-arc table). */
 size_t sphint_workspace_size(int64_t nnz);
 
 /*

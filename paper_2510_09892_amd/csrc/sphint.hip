@@ -25,6 +25,18 @@ __global__ void k_init(uint32_t* ws, uint64_t* status, int64_t ntiles, int64_t* 
   for (int64_t k = t; k < ntiles; k += (int64_t)gridDim.x * blockDim.x) status[k] = 0ull;
 }
 
+}  // namespace
+
+namespace sphint {
+__global__ void k_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs, int64_t nnz,
+                            uint32_t* __restrict__ parc) {
+  fill_pair_arcs(off, n_arcs, nnz, parc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                 (int64_t)gridDim.x * blockDim.x);
+}
+}  // namespace sphint
+
+namespace {
+
 constexpr int WPPT_SINGLE = 4;       // pairs per lane of single calls (wavefront tile = 256)
 constexpr int WG_PER_CU_SINGLE = 4;  // resident workgroups per CU of the persistent grid
 
@@ -73,10 +85,7 @@ hipError_t launch_main(const KArgs& k, hipStream_t st) {
 
 }  // namespace
 
-extern "C" size_t sphint_workspace_size(int64_t nnz) {
-  int64_t t = wave_tiles_for(nnz < 0 ? 0 : nnz, 1);  // the most tiles any schedule uses
-  return WS_HEADER + 8 * (size_t)(t > 0 ? t : 1);
-}
+extern "C" size_t sphint_workspace_size(int64_t nnz) { return workspace_bytes_for(nnz); }
 
 extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
                                              sphint_pts_soa p2, const double* lat_z,
@@ -108,8 +117,11 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
   if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
   if (nnz == 0) return chain.end() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
 
+  uint32_t* parc = (uint32_t*)((char*)workspace + WS_HEADER + 8 * status_words_for(nnz));
   KArgs k = make_args(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out, out_count,
-                      out_flags, out_total, ws, status, ntiles);
+                      out_flags, out_total, ws, status, ntiles, parc);
+  if (lat_offsets && launch_pair_arcs(lat_offsets, n_arcs, nnz, parc, st) != hipSuccess)
+    return SPHINT_E_HIP;
   if (prof_start && hipEventRecord(prof_start, st) != hipSuccess) return SPHINT_E_HIP;
   const bool csr = lat_offsets != nullptr;
   hipError_t e;

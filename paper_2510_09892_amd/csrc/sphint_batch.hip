@@ -32,7 +32,7 @@ template <int MODE, int PPT, bool CSR>
 __global__ __launch_bounds__(BLOCK) void k_batch(const KArgs* __restrict__ args,
                                                  const int64_t* __restrict__ tile_base,
                                                  int n_meshes, int64_t total_tiles) {
-  __shared__ WgShared<MODE, PPT> sh;
+  __shared__ WgShared<MODE, PPT, CSR> sh;
   if (threadIdx.x == 0) sh.lock = 0;
   __syncthreads();
   const int wave = threadIdx.x >> 6;
@@ -83,6 +83,7 @@ struct sphint_plan {
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   std::vector<int64_t> tile_base;
+  std::vector<uint32_t*> parc;  // CSR: each mesh's pair-to-arc table in d_ws
   int64_t total_tiles = 0;
   bool csr = false;  // every mesh of a plan has the same form
   hipStream_t capture_stream = nullptr;
@@ -126,7 +127,10 @@ sphint_status layout(sphint_plan* p) {
     p->tile_base[m + 1] = p->tile_base[m] + wave_tiles_for(p->meshes[m].nnz, p->ppt);
   p->total_tiles = p->tile_base[n];
   if (p->total_tiles > 0x7fffffffLL) return SPHINT_E_INVAL;
-  const size_t need = WS_HEADER + 8 * (size_t)(p->total_tiles > 0 ? p->total_tiles : 1);
+  int64_t nnz_all = 0;
+  for (int m = 0; m < n; ++m) nnz_all += p->meshes[m].nnz;
+  const size_t status_words = (size_t)(p->total_tiles > 0 ? p->total_tiles : 1);
+  const size_t need = WS_HEADER + 8 * status_words + (p->csr ? 4 * (size_t)nnz_all : 0);
   if (need > p->ws_bytes) {
     if (p->d_ws) (void)hipFree(p->d_ws);
     p->d_ws = nullptr;
@@ -135,12 +139,16 @@ sphint_status layout(sphint_plan* p) {
   }
   uint32_t* ws = (uint32_t*)p->d_ws;
   uint64_t* status = (uint64_t*)((char*)p->d_ws + WS_HEADER);
+  uint32_t* parc = (uint32_t*)((char*)p->d_ws + WS_HEADER + 8 * status_words);
   std::vector<KArgs> h(n);
+  p->parc.assign(n, nullptr);
   for (int m = 0; m < n; ++m) {
     const sphint_mesh_desc& d = p->meshes[m];
+    p->parc[m] = p->csr ? parc : nullptr;
     h[m] = make_args(d.n_arcs, d.p1, d.p2, d.lat_z, d.n_lat, d.lat_offsets, d.lat_idx, d.nnz,
                      d.out, d.out_count, d.out_flags, d.out_total, ws,
-                     status + p->tile_base[m], p->tile_base[m + 1] - p->tile_base[m]);
+                     status + p->tile_base[m], p->tile_base[m + 1] - p->tile_base[m], parc);
+    if (p->csr) parc += d.nnz;
   }
   if (hipMemcpy(p->d_args, h.data(), sizeof(KArgs) * n, hipMemcpyHostToDevice) != hipSuccess)
     return SPHINT_E_HIP;
@@ -178,6 +186,12 @@ sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
   if (ib == 0) ib = 1;
   hipLaunchKernelGGL(k_batch_init, dim3(ib), dim3(256), 0, st, ws, status, p->total_tiles,
                      p->d_args, n);
+  if (p->csr)
+    for (int m = 0; m < n; ++m) {
+      const sphint_mesh_desc& d = p->meshes[m];
+      if (launch_pair_arcs(d.lat_offsets, d.n_arcs, d.nnz, p->parc[m], st) != hipSuccess)
+        return SPHINT_E_HIP;
+    }
   if (p->total_tiles > 0) {
     // every wavefront of the grid must be resident at once (see k_batch)
     const int res = resident_per_cu(p, p->ppt);

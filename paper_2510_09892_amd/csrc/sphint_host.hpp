@@ -22,6 +22,30 @@ inline int64_t wave_tiles_for(int64_t nnz, int wppt) {
 
 inline bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
+// Workspace of one call over nnz pairs: header, one status word per tile of the finest
+// schedule (64 pairs), then the CSR pair-to-arc table (4 bytes per pair).
+inline size_t status_words_for(int64_t nnz) {
+  const int64_t t = wave_tiles_for(nnz < 0 ? 0 : nnz, 1);
+  return (size_t)(t > 0 ? t : 1);
+}
+inline size_t workspace_bytes_for(int64_t nnz) {
+  return WS_HEADER + 8 * status_words_for(nnz) + 4 * (size_t)(nnz > 0 ? nnz : 0);
+}
+
+// One thread per arc (grid-stride): the CSR pair-to-arc table.
+__global__ void k_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs, int64_t nnz,
+                            uint32_t* __restrict__ parc);
+
+inline hipError_t launch_pair_arcs(const int64_t* off, int64_t n_arcs, int64_t nnz,
+                                   uint32_t* parc, hipStream_t st) {
+  if (n_arcs <= 0 || nnz <= 0) return hipSuccess;
+  int64_t blocks = (n_arcs + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_pair_arcs, dim3((unsigned)blocks), dim3(256), 0, st, off, n_arcs, nnz,
+                     parc);
+  return hipGetLastError();
+}
+
 // Argument checks shared by the single-call and batched paths.
 inline sphint_status validate(int64_t n_arcs, const sphint_pts_soa& p1, const sphint_pts_soa& p2,
                               const double* lat_z, int64_t n_lat, const int64_t* off,
@@ -33,6 +57,7 @@ inline sphint_status validate(int64_t n_arcs, const sphint_pts_soa& p1, const sp
   if (csr) {
     if (!off || (!idx && nnz > 0)) return SPHINT_E_INVAL;
     if (nnz > 0 && (n_arcs == 0 || n_lat == 0 || !lat_z)) return SPHINT_E_INVAL;
+    if (n_arcs >= ((int64_t)1 << 32)) return SPHINT_E_INVAL;  // arc ids are 32-bit
   } else {
     if (n_lat != n_arcs || nnz != n_arcs) return SPHINT_E_INVAL;
   }
@@ -49,7 +74,7 @@ inline KArgs make_args(int64_t n_arcs, const sphint_pts_soa& p1, const sphint_pt
                        const double* lat_z, int64_t n_lat, const int64_t* off,
                        const int32_t* idx, int64_t nnz, const sphint_hits& out,
                        uint8_t* out_count, uint8_t* out_flags, int64_t* out_total,
-                       uint32_t* ws, uint64_t* status, int64_t ntiles) {
+                       uint32_t* ws, uint64_t* status, int64_t ntiles, uint32_t* parc) {
   KArgs k;
   k.n_arcs = n_arcs;
   k.n_lat = n_lat;
@@ -59,6 +84,7 @@ inline KArgs make_args(int64_t n_arcs, const sphint_pts_soa& p1, const sphint_pt
   k.lat_z = lat_z;
   k.off = off;
   k.idx = off ? idx : nullptr;
+  k.parc = off ? parc : nullptr;
   k.ox = out.x; k.oy = out.y; k.opair = out.pair; k.oroot = out.root; k.cap = out.capacity;
   k.ocount = out_count;
   k.oflags = out_flags;

@@ -33,6 +33,7 @@ struct KArgs {
   const double* lat_z;
   const int64_t* off;
   const int32_t* idx;
+  const uint32_t* parc;  // CSR: arc of each pair (in the workspace)
   double *ox, *oy;
   int64_t* opair;
   uint8_t* oroot;
@@ -45,6 +46,14 @@ struct KArgs {
   int64_t ntiles;
 };
 
+// The same pointer in the global address space: argument pointers read from memory (the
+// batched kernel's per-mesh tables) are otherwise generic, and generic (flat) accesses
+// are slower and share a wait counter with scalar loads.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // Runs fn() for every lane of the wavefront with need == true, one lane at a time.
 template <class F>
 __device__ __forceinline__ void resolve_serial(bool need, F&& fn) {
@@ -55,17 +64,6 @@ __device__ __forceinline__ void resolve_serial(bool need, F&& fn) {
     if (lane == l) fn();
     m &= m - 1;
   }
-}
-
-// Largest a in [lo, hi] with off[a] <= k: the arc owning CSR entry k.
-__device__ __forceinline__ int64_t find_arc(const int64_t* __restrict__ off, int64_t lo,
-                                            int64_t hi, int64_t k) {
-  while (lo < hi) {
-    int64_t mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= k) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
 }
 
 
@@ -222,7 +220,7 @@ constexpr int scan_k() {
   return (int)(sizeof(WaveStage<WPPT>) / (64 * sizeof(uint64_t))) - 1;
 }
 
-template <int MODE, int WPPT>
+template <int MODE, int WPPT, bool CSR>
 struct WgShared {
   WaveStage<WPPT> stage[NWAVE];
   double arena[MODE ? xp::ARENA : 1];
@@ -252,33 +250,23 @@ struct RowIn {
   bool valid;
 };
 
-// Per-tile context for loading rows: the tile's first pair and, for CSR calls, the range
-// of arcs its pairs belong to.
+// Per-tile context for loading rows: the tile's first pair.
 struct TileCtx {
-  int64_t base, arc_lo, arc_hi;
+  int64_t base;
 };
 
 template <int WPPT, bool CSR>
 __device__ __forceinline__ TileCtx tile_ctx(const KArgs& a, int64_t tile) {
-  const int lane = __lane_id();
   TileCtx c;
   c.base = tile * (int64_t)(64 * WPPT);
-  c.arc_lo = c.arc_hi = 0;
-  if (CSR) {
-    int64_t first = c.base < a.nnz ? c.base : a.nnz - 1;
-    int64_t last = c.base + 64 * WPPT - 1 < a.nnz ? c.base + 64 * WPPT - 1 : a.nnz - 1;
-    int64_t v = 0;
-    if (lane == 0) v = find_arc(a.off, 0, a.n_arcs - 1, first);
-    if (lane == 1) v = find_arc(a.off, 0, a.n_arcs - 1, last);
-    c.arc_lo = __shfl(v, 0, 64);
-    c.arc_hi = __shfl(v, 1, 64);
-  }
   return c;
 }
 
 // Loads one row without branches: lanes past the end read the last pair (and are marked
 // invalid), so the compiler can count outstanding loads exactly and the row fetched ahead
-// stays in flight while the current row is evaluated.
+// stays in flight while the current row is evaluated.  CSR calls take each pair's arc from
+// the pair-to-arc table that k_pair_arcs wrote (clamped, so malformed offsets cannot send
+// a read out of bounds).
 template <bool CSR>
 __device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int j) {
   RowIn r;
@@ -287,24 +275,39 @@ __device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int 
   const int64_t ii = r.valid ? r.i : a.nnz - 1;
   int64_t arc = ii;
   if (CSR) {
-    arc = find_arc(a.off, c.arc_lo, c.arc_hi, ii);
-    const int32_t li = a.idx[ii];
+    const int64_t pa = (int64_t)gptr(a.parc)[ii];
+    arc = pa < a.n_arcs ? pa : a.n_arcs - 1;
+    const int32_t li = gptr(a.idx)[ii];
     const bool ok = li >= 0 && li < a.n_lat;
-    const double z = a.lat_z[ok ? li : 0];
+    const double z = gptr(a.lat_z)[ok ? li : 0];
     r.z0 = ok ? z : __builtin_nan("");
   } else {
-    r.z0 = a.lat_z[ii];
+    r.z0 = gptr(a.lat_z)[ii];
   }
-  r.x1 = a.x1[arc]; r.y1 = a.y1[arc]; r.z1 = a.z1[arc];
-  r.x2 = a.x2[arc]; r.y2 = a.y2[arc]; r.z2 = a.z2[arc];
+  r.x1 = gptr(a.x1)[arc]; r.y1 = gptr(a.y1)[arc]; r.z1 = gptr(a.z1)[arc];
+  r.x2 = gptr(a.x2)[arc]; r.y2 = gptr(a.y2)[arc]; r.z2 = gptr(a.z2)[arc];
   return r;
+}
+
+// CSR pair-to-arc table: parc[k] = the arc owning entry k, for the arcs [a_begin, a_end)
+// handled by this launch (one thread per arc, grid-stride; offsets read once, coalesced).
+// Entries are written only inside [0, nnz).
+__device__ __forceinline__ void fill_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs,
+                                               int64_t nnz, uint32_t* __restrict__ parc,
+                                               int64_t a, int64_t stride) {
+  for (; a < n_arcs; a += stride) {
+    int64_t b = off[a], e = off[a + 1];
+    b = b > 0 ? b : 0;
+    e = e < nnz ? e : nnz;
+    for (int64_t q = b; q < e; ++q) parc[q] = (uint32_t)a;
+  }
 }
 
 // Evaluates one row already loaded, writes its counts and flags, and accumulates the
 // tile's in-order hit offsets.
-template <int MODE, int WPPT>
+template <int MODE, int WPPT, class Shared>
 __device__ __forceinline__ void eval_row(const KArgs& a, const RowIn& in, int j, TileRegs<WPPT>& r,
-                                         WgShared<MODE, WPPT>& sh) {
+                                         Shared& sh) {
   const int lane = __lane_id();
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   PairOut& o = r.o[j];
@@ -324,8 +327,8 @@ __device__ __forceinline__ void eval_row(const KArgs& a, const RowIn& in, int j,
   const int cnt = in.valid ? o.count : 0;
   o.count = cnt;
   if (in.valid) {
-    a.ocount[in.i] = (uint8_t)cnt;
-    if (a.oflags) a.oflags[in.i] = (uint8_t)o.flags;
+    gptr(a.ocount)[in.i] = (uint8_t)cnt;
+    if (a.oflags) gptr(a.oflags)[in.i] = (uint8_t)o.flags;
   }
   const unsigned long long b1 = __ballot(cnt >= 1);
   const unsigned long long b2 = __ballot(cnt >= 2);
@@ -365,10 +368,10 @@ __device__ __forceinline__ void flush_tile(const KArgs& a, int64_t tile, int cou
   for (int k = lane; k < count; k += 64) {
     const int64_t pos = prefix + k;
     if (pos < a.cap) {
-      a.ox[pos] = st.x[k];
-      a.oy[pos] = st.y[k];
-      a.opair[pos] = base + st.pair[k];
-      a.oroot[pos] = st.root[k];
+      gptr(a.ox)[pos] = st.x[k];
+      gptr(a.oy)[pos] = st.y[k];
+      gptr(a.opair)[pos] = base + st.pair[k];
+      gptr(a.oroot)[pos] = st.root[k];
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -383,7 +386,8 @@ __device__ __forceinline__ void flush_tile(const KArgs& a, int64_t tile, int cou
 // its offset.  Rows evaluated after that point go straight to the staging buffer, so at most
 // FLUSH_AT rows of results are held in registers.
 template <int MODE, int WPPT, bool CSR, int FLUSH_AT, class Next>
-__device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT>& sh, Next&& next) {
+__device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT, CSR>& sh,
+                                          Next&& next) {
   static_assert(FLUSH_AT >= 1 && FLUSH_AT <= WPPT, "flush point inside the tile");
   const int wave = threadIdx.x >> 6;
   WaveStage<WPPT>& st = sh.stage[wave];
@@ -395,6 +399,7 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
   TileRegs<WPPT> r;
   bool have = next(m, tile);
   if (!have) return;
+  m = __builtin_amdgcn_readfirstlane(m);  // wavefront-uniform: the arguments load as scalars
   TileCtx ctx = tile_ctx<WPPT, CSR>(args[m], tile), ctx2;
   RowIn cur = load_row<CSR>(args[m], ctx, 0), nxt;
   while (have) {
@@ -411,6 +416,7 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
           m2 = m;
           tile2 = tile;
         }
+        m2 = __builtin_amdgcn_readfirstlane(m2);
         ctx2 = tile_ctx<WPPT, CSR>(args[m2], tile2);
         nxt = load_row<CSR>(args[m2], ctx2, 0);
       }
@@ -464,7 +470,7 @@ constexpr int flush_at() {
 // c of the other W takes tiles c, c + W, c + 2W, ...
 template <int MODE, int WPPT, bool CSR>
 __global__ __launch_bounds__(BLOCK) void k_intersect_w(KArgs a) {
-  __shared__ WgShared<MODE, WPPT> sh;
+  __shared__ WgShared<MODE, WPPT, CSR> sh;
   if (threadIdx.x == 0) sh.lock = 0;
   __syncthreads();
   const int wave = threadIdx.x >> 6;

@@ -42,10 +42,11 @@ def test_pure_calls():
     lib = sphint.load()
     assert lib.sphint_version().decode().startswith("sphint")
     assert lib.sphint_status_string(0).decode() == "ok"
+    # header + one status word per 64 pairs + a 4-byte pair-to-arc entry per pair
     assert lib.sphint_workspace_size(0) == 256 + 8
-    assert lib.sphint_workspace_size(64) == 256 + 8
-    assert lib.sphint_workspace_size(65) == 256 + 16
-    assert lib.sphint_workspace_size(10_000_000) == 256 + 8 * 156250
+    assert lib.sphint_workspace_size(64) == 256 + 8 + 4 * 64
+    assert lib.sphint_workspace_size(65) == 256 + 16 + 4 * 65
+    assert lib.sphint_workspace_size(10_000_000) == 256 + 8 * 156250 + 4 * 10_000_000
 
 
 def _call(**kw):
