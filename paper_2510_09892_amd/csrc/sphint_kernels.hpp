@@ -212,14 +212,15 @@ struct WaveStage {
   uint8_t root[2 * 64 * WPPT];
 };
 
-// Workgroup LDS: one staging buffer per wavefront and one exact-arithmetic arena shared by
-// the workgroup's wavefronts under a lock (exact evaluations are rare).
 // Tiles per scanner lane per pass: the scanner borrows its own (unused) staging buffer.
 template <int WPPT>
 constexpr int scan_k() {
   return (int)(sizeof(WaveStage<WPPT>) / (64 * sizeof(uint64_t))) - 1;
 }
 
+// Workgroup LDS: one staging buffer per wavefront and one exact-arithmetic arena shared by
+// the workgroup's wavefronts under a lock (exact evaluations are rare, and the arena's short
+// dependent accesses want LDS latency).
 template <int MODE, int WPPT, bool CSR>
 struct WgShared {
   WaveStage<WPPT> stage[NWAVE];

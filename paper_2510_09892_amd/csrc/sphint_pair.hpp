@@ -318,85 +318,95 @@ __host__ __device__ __forceinline__ int height_cmp(double z0, double z, double n
   return UNDECIDED;
 }
 
-// Alg. 2 (CompDot) over six precomputed TwoProducts, in Alg. 8's term order.
-__host__ __device__ __forceinline__ double comp_dot6(dd t0, dd t1, dd t2, dd t3, dd t4, dd t5) {
-  double p = t0.hi, s = t0.lo;
-  dd q = two_sum(p, t1.hi); p = q.hi; s = s + (q.lo + t1.lo);
-  q = two_sum(p, t2.hi); p = q.hi; s = s + (q.lo + t2.lo);
-  q = two_sum(p, t3.hi); p = q.hi; s = s + (q.lo + t3.lo);
-  q = two_sum(p, t4.hi); p = q.hi; s = s + (q.lo + t4.lo);
-  q = two_sum(p, t5.hi); p = q.hi; s = s + (q.lo + t5.lo);
+// Alg. 2 (CompDot) over six TwoProducts in Alg. 8's term order, split in two: the running
+// sum over the first two terms (the z0 terms, the same for both roots) and the rest.
+struct CdState {
+  double p, s;
+};
+
+__host__ __device__ __forceinline__ CdState comp_dot_head(dd t0, dd t1) {
+  const dd q = two_sum(t0.hi, t1.hi);
+  return {q.hi, t0.lo + (q.lo + t1.lo)};
+}
+
+// Continues the sum with sg * t2 ... sg * t5 (sg = +1 or -1; negating a TwoProduct's pair
+// negates both parts exactly, so this equals CompDot over the negated products).
+__host__ __device__ __forceinline__ double comp_dot_tail(CdState c, dd t2, dd t3, dd t4, dd t5,
+                                                         double sg) {
+  double p = c.p, s = c.s;
+  dd q = two_sum(p, sg * t2.hi); p = q.hi; s = s + (q.lo + sg * t2.lo);
+  q = two_sum(p, sg * t3.hi); p = q.hi; s = s + (q.lo + sg * t3.lo);
+  q = two_sum(p, sg * t4.hi); p = q.hi; s = s + (q.lo + sg * t4.lo);
+  q = two_sum(p, sg * t5.hi); p = q.hi; s = s + (q.lo + sg * t5.lo);
   return p + s;
 }
 
-__host__ __device__ __forceinline__ dd neg(dd v) { return {-v.hi, -v.lo}; }
-
-// Alg. 8 lines 12, 17, 22-25 for the roots of o (o.count, o.r0, o.r1 already set).  The
-// lower-sign root is AccuX with (s, e_s) negated (negation is exact).  The two z0 terms of
-// each CompDot do not depend on the root and are formed once.
+// Alg. 8's numerators and divisions for the roots of a pair (o.count, o.r0, o.r1 set).  The
+// lower-sign root is AccuX with (s, e_s) negated, so its TwoProducts are the exact negations
+// of the upper root's: the products are formed once, with the sign of the first root, and a
+// second root (always the other sign) reuses them negated.  The z0 terms open both CompDots.
 __host__ __device__ __forceinline__ void points_eft(const ArcEft& a, double z0, const S2Eft& s2,
                                                     PairOut& o) {
   const dd sq = acc_sqrt(s2.ss, s2.ess);
-  const dd fx0 = two_prod(a.Fx, z0), fx1 = two_prod(a.eFx, z0);
-  const dd fy0 = two_prod(a.Fy, z0), fy1 = two_prod(a.eFy, z0);
-  for (int k = 0; k < o.count; ++k) {
-    const bool plus = (k == 0 ? o.r0 : o.r1) == ROOT_PLUS;
-    const double sb = plus ? sq.hi : -sq.hi;
-    const double es = plus ? sq.lo : -sq.lo;
-    const double xn = comp_dot6(fx0, fx1, two_prod(a.ny, sb), two_prod(a.eny, sb),
-                                two_prod(a.ny, es), two_prod(a.eny, es));
-    const double yn = comp_dot6(fy0, fy1, two_prod(-a.nx, sb), two_prod(-a.enx, sb),
-                                two_prod(-a.nx, es), two_prod(-a.enx, es));
-    const double px = -(xn / a.S2);
-    const double py = -(yn / a.S2);
-    if (k == 0) {
-      o.px0 = px;
-      o.py0 = py;
-    } else {
-      o.px1 = px;
-      o.py1 = py;
-    }
+  const CdState hx = comp_dot_head(two_prod(a.Fx, z0), two_prod(a.eFx, z0));
+  const CdState hy = comp_dot_head(two_prod(a.Fy, z0), two_prod(a.eFy, z0));
+  const bool plus0 = o.r0 == ROOT_PLUS;
+  const double sb = plus0 ? sq.hi : -sq.hi;
+  const double es = plus0 ? sq.lo : -sq.lo;
+  const dd x2 = two_prod(a.ny, sb), x3 = two_prod(a.eny, sb);
+  const dd x4 = two_prod(a.ny, es), x5 = two_prod(a.eny, es);
+  const dd y2 = two_prod(-a.nx, sb), y3 = two_prod(-a.enx, sb);
+  const dd y4 = two_prod(-a.nx, es), y5 = two_prod(-a.enx, es);
+  o.px0 = -(comp_dot_tail(hx, x2, x3, x4, x5, 1.0) / a.S2);
+  o.py0 = -(comp_dot_tail(hy, y2, y3, y4, y5, 1.0) / a.S2);
+  if (o.count == 2) {
+    o.px1 = -(comp_dot_tail(hx, x2, x3, x4, x5, -1.0) / a.S2);
+    o.py1 = -(comp_dot_tail(hy, y2, y3, y4, y5, -1.0) / a.S2);
   }
 }
 
 // ====================================================================== pair drivers
 
-// Exact signs of the five predicates of one pair (exact_sign), for the forced evaluation.
-struct ExactSigns {
-  int d1, d2, s2, h1, h2;  // h_i = sign(z0^2 |x_i|^2 - z_i^2)
+// The five decisions of one pair: the slopes d1, d2 (sign of dz/dt at the endpoints), the
+// existence sign s2 (sign of s^2) and the height comparisons c1, c2 (sign(z0 - z_i/|x_i|));
+// UNDECIDED where a filter could not decide.
+struct Decisions {
+  int d1, d2, s2, c1, c2;
 };
 
-__host__ __device__ __forceinline__ ExactSigns exact_signs(double x1, double y1, double z1,
-                                                           double x2, double y2, double z2,
-                                                           double z0, double* arena,
-                                                           bool& overflow) {
-  ExactSigns e;
-  int r[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    r[k] = exact_sign(k, x1, y1, z1, x2, y2, z2, z0, arena);
-    if (r[k] == 2) {
-      overflow = true;
-      r[k] = 0;
+// Replaces every UNDECIDED decision by its exact sign (exact_sign in the arena; a height
+// comparison is undecided only when z0 and z_i are nonzero with the same sign, and then
+// c_i = sgn(z0) * sign(z0^2 |x_i|^2 - z_i^2)).  Returns false if an expansion exceeded the
+// arena (the sign is then taken as 0).
+__host__ __device__ __forceinline__ bool resolve_exact(Decisions& d, double x1, double y1,
+                                                       double z1, double x2, double y2,
+                                                       double z2, double z0, double* arena) {
+  bool ok = true;
+  auto ex = [&](int which) {
+    int r = exact_sign(which, x1, y1, z1, x2, y2, z2, z0, arena);
+    if (r == 2) {
+      ok = false;
+      r = 0;
     }
-  }
-  e.s2 = r[PRED_S2];
-  e.d1 = r[PRED_D1];
-  e.d2 = r[PRED_D2];
-  e.h1 = r[PRED_H1];
-  e.h2 = r[PRED_H2];
-  return e;
+    return r;
+  };
+  if (d.s2 == UNDECIDED) d.s2 = ex(PRED_S2);
+  if (d.d1 == UNDECIDED) d.d1 = ex(PRED_D1);
+  if (d.d2 == UNDECIDED) d.d2 = ex(PRED_D2);
+  if (d.c1 == UNDECIDED) d.c1 = sgn(z0) * ex(PRED_H1);
+  if (d.c2 == UNDECIDED) d.c2 = sgn(z0) * ex(PRED_H2);
+  return ok;
 }
 
-// One pair in EFT mode.  FORCED == false: every decision comes from the floating-point
-// filters; if one cannot decide, the result carries F_NEEDEXACT and nothing else is valid.
-// FORCED == true: the decisions are the exact signs `ex` (the filters are skipped), so the
-// result is final.  Both evaluate the same AccuX arithmetic.
+// One pair in EFT mode.  FORCED == false: the decisions come from the floating-point filters
+// and are stored in `dec`; if one cannot be decided (and the pair is not certainly without
+// intersection), the result carries F_NEEDEXACT and nothing else of it is valid.
+// FORCED == true: the decisions are taken from `dec` (all decided), so the result is final.
+// Both evaluate the same AccuX arithmetic.
 template <bool FORCED>
 __host__ __device__ __forceinline__ PairOut eval_eft_core(bool valid, double x1, double y1,
                                                           double z1, double x2, double y2,
-                                                          double z2, double z0,
-                                                          const ExactSigns& ex) {
+                                                          double z2, double z0, Decisions& dec) {
   PairOut o;
   o.count = 0;
   o.r0 = o.r1 = 0;
@@ -413,32 +423,24 @@ __host__ __device__ __forceinline__ PairOut eval_eft_core(bool valid, double x1,
     o.flags = F_NONFINITE;
     return o;
   }
-  const int d1 = FORCED ? ex.d1 : d_sign(A, x1, y1);
-  const int d2 = FORCED ? ex.d2 : d_sign(A, x2, y2);
-  S2Eft S = s2_eft(A, z0);
-  if (FORCED) S.sign = ex.s2;
-  if (!FORCED && (d1 == UNDECIDED || d2 == UNDECIDED || S.sign == UNDECIDED)) {
-    o.flags = F_NEEDEXACT;
-    return o;
-  }
-  if (S.sign < 0) return o;
-  const dd C = two_prod(z0, z0);
-  int c1, c2;
-  if (FORCED) {
-    // sign(z0 - z/|x|): decided by the signs of z0 and z, else by sgn(z0) * h
-    c1 = z0 == 0.0 ? -sgn(A.z1) : ((A.z1 == 0.0 || (z0 > 0.0) != (A.z1 > 0.0)) ? sgn(z0) : sgn(z0) * ex.h1);
-    c2 = z0 == 0.0 ? -sgn(A.z2) : ((A.z2 == 0.0 || (z0 > 0.0) != (A.z2 > 0.0)) ? sgn(z0) : sgn(z0) * ex.h2);
-  } else {
-    c1 = height_cmp(z0, A.z1, A.n21, A.zz1, x1, y1, C);
-    c2 = height_cmp(z0, A.z2, A.n22, A.zz2, x2, y2, C);
-    if (c1 == UNDECIDED || c2 == UNDECIDED) {
+  const S2Eft S = s2_eft(A, z0);
+  if (!FORCED) dec.s2 = S.sign;
+  if (dec.s2 < 0) return o;  // certainly no intersection (UNDECIDED is positive)
+  if (!FORCED) {
+    dec.d1 = d_sign(A, x1, y1);
+    dec.d2 = d_sign(A, x2, y2);
+    const dd C = two_prod(z0, z0);
+    dec.c1 = height_cmp(z0, A.z1, A.n21, A.zz1, x1, y1, C);
+    dec.c2 = height_cmp(z0, A.z2, A.n22, A.zz2, x2, y2, C);
+    if (dec.s2 == UNDECIDED || dec.d1 == UNDECIDED || dec.d2 == UNDECIDED ||
+        dec.c1 == UNDECIDED || dec.c2 == UNDECIDED) {
       o.flags = F_NEEDEXACT;
       return o;
     }
   }
-  const bool tangent = S.sign == 0;
+  const bool tangent = dec.s2 == 0;
   o.flags = F_EXISTS | (tangent ? F_TANGENT : 0u) | (FORCED ? F_FALLBACK : 0u);
-  o.count = hit_rule(d1, d2, c1, c2, tangent, o.r0, o.r1);
+  o.count = hit_rule(dec.d1, dec.d2, dec.c1, dec.c2, tangent, o.r0, o.r1);
   if (o.count) points_eft(A, z0, S, o);
   return o;
 }
@@ -446,20 +448,20 @@ __host__ __device__ __forceinline__ PairOut eval_eft_core(bool valid, double x1,
 // EFT evaluation with exact decisions.  resolve(need, fn) must run fn() on every caller
 // with need == true (the GPU runs them one lane at a time per wavefront; the CPU build runs
 // them at once); all callers of one wavefront must reach the call.  The fast evaluation
-// runs for every pair; only pairs a filter could not decide get their five exact signs
-// (in the arena) and a forced re-evaluation.
+// runs for every pair; a pair with undecided filters gets exact signs for exactly those
+// decisions (in the arena) and a forced re-evaluation.
 template <class Resolve>
 __host__ __device__ __forceinline__ PairOut eval_eft(bool valid, double x1, double y1, double z1,
                                                      double x2, double y2, double z2, double z0,
                                                      double* arena, Resolve&& resolve) {
-  ExactSigns ex = {0, 0, 0, 0, 0};
-  PairOut o = eval_eft_core<false>(valid, x1, y1, z1, x2, y2, z2, z0, ex);
+  Decisions dec = {0, 0, 0, 0, 0};
+  PairOut o = eval_eft_core<false>(valid, x1, y1, z1, x2, y2, z2, z0, dec);
   const bool need = (o.flags & F_NEEDEXACT) != 0;
-  bool overflow = false;
-  resolve(need, [&] { ex = exact_signs(x1, y1, z1, x2, y2, z2, z0, arena, overflow); });
+  bool ok = true;
+  resolve(need, [&] { ok = resolve_exact(dec, x1, y1, z1, x2, y2, z2, z0, arena); });
   if (need) {
-    o = eval_eft_core<true>(valid, x1, y1, z1, x2, y2, z2, z0, ex);
-    if (overflow) o.flags |= F_INTERNAL;
+    o = eval_eft_core<true>(valid, x1, y1, z1, x2, y2, z2, z0, dec);
+    if (!ok) o.flags |= F_INTERNAL;
   }
   return o;
 }
