@@ -131,14 +131,20 @@ __device__ __forceinline__ void scan_tiles(uint64_t* status, int64_t ntiles, int
   uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   unsigned polls = 0;
   while (t < ntiles) {
-    // coalesced loads: word k * 64 + lane of the window goes to lds[(q / K) * P + q % K]
+    // coalesced loads, all issued before the first is used (no branch around them: indices
+    // past the end read the last state, and are zeroed); word k * 64 + lane of the window
+    // goes to lds[(q / K) * P + q % K]
+    uint64_t wv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int64_t j = t + k * 64 + lane;
+      wv[k] = __hip_atomic_load(status + (j < ntiles ? j : ntiles - 1), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int q = k * 64 + lane;
-      const int64_t j = t + q;
-      uint64_t w = 0;
-      if (j < ntiles) w = __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      lds[(q / K) * P + q % K] = w;
+      lds[(q / K) * P + q % K] = t + q < ntiles ? wv[k] : 0ull;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
