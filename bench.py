@@ -308,7 +308,9 @@ def main():
     r = res[head]
     value = n * args.steps / r["wall_s"]
     hits = r["total"]
-    kernel = f"sphint::k_intersect_w<{1 if head == 'eft' else 0},4,{'true' if csr else 'false'}>"
+    kname = lambda m: (f"sphint::k_intersect_w<{1 if m == 'eft' else 0},{3 if m == 'eft' else 4},"
+                       f"{'true' if csr else 'false'}>")
+    kernel = kname(head)
     tag = f"k_intersect_w_{head}_{args.workload}"
     roof = roofline(head, r, n, bytes_in + BYTES_PER_HIT * hits, kernel, tag)
 
@@ -334,7 +336,7 @@ def main():
         line["naive"] = {"value": nv, "ms_per_step": rn["wall_s"] / args.steps * 1e3,
                          "kernel_ms": statistics.mean(rn["kernel_ms"]), "hits": rn["total"],
                          "roofline": roofline("naive", rn, n, bytes_in + BYTES_PER_HIT * rn["total"],
-                                              kernel.replace("<1,", "<0,"),
+                                              kname("naive"),
                                               f"k_intersect_w_naive_{args.workload}")}
         line["eft_over_naive"] = value / nv
     if not args.no_latency and args.workload == "ill1e7":

@@ -164,7 +164,7 @@ typedef struct sphint_plan sphint_plan;
  */
 sphint_status sphint_batch_plan_create(const sphint_mesh_desc *meshes, int n_meshes,
                                        sphint_mode mode, sphint_plan **plan);
-/* Times the plan's candidate schedules (pairs per thread 1, 2, 4 x persistent grid sizes)
+/* Times the plan's candidate schedules (pairs per thread 1-4 x persistent grid sizes)
  * by running the whole batch on `stream`, keeps the fastest, and synchronizes the stream;
  * reads/appends a text cache at cache_path (may be NULL) keyed by the plan's shape.  The
  * batch's outputs are overwritten (with the same values). */
@@ -177,7 +177,7 @@ sphint_status sphint_batch_launch(sphint_plan *plan, void *stream);
  * since the grid's wavefronts must all be resident). */
 sphint_status sphint_batch_params(const sphint_plan *plan, int *pairs_per_thread,
                                   int *wg_per_cu);
-/* Sets the schedule by hand (pairs_per_thread 1, 2 or 4; wg_per_cu >= 0, capped at what a CU
+/* Sets the schedule by hand (pairs_per_thread 1 to 4; wg_per_cu >= 0, capped at what a CU
  * holds) instead of the autotuner's choice; the next launch re-captures the graph. */
 sphint_status sphint_batch_set_params(sphint_plan *plan, int pairs_per_thread, int wg_per_cu);
 /* After the stream has completed a launch of the plan: SPHINT_E_DEVICE if a kernel of that

@@ -37,7 +37,14 @@ __global__ void k_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs, int
 
 namespace {
 
-constexpr int WPPT_SINGLE = 4;       // pairs per lane of single calls (wavefront tile = 256)
+// Pairs per lane of single calls: the EFT evaluation is compute-heavy and gains from four
+// resident waves per SIMD, which its 3-row tiles (192 pairs, 29-33 KB of LDS per
+// workgroup) allow; the memory-bound naive evaluation does better with fewer, larger
+// 4-row tiles (256 pairs).
+template <int MODE>
+constexpr int wppt_single() {
+  return MODE ? 3 : 4;
+}
 constexpr int WG_PER_CU_SINGLE = 4;  // resident workgroups per CU of the persistent grid
 
 thread_local hipEvent_t prof_start = nullptr, prof_stop = nullptr;
@@ -57,13 +64,14 @@ int device_cus() {
   return cached[dev];
 }
 
-// Workgroups of k_intersect_w<MODE, WPPT_SINGLE, CSR> one CU holds at once (queried once).
+// Workgroups of k_intersect_w<MODE, wppt_single<MODE>(), CSR> one CU holds at once
+// (queried once).
 template <int MODE, bool CSR>
 int resident_per_cu() {
   static int cached = 0;
   if (!cached) {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_intersect_w<MODE, WPPT_SINGLE, CSR>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_intersect_w<MODE, wppt_single<MODE>(), CSR>,
                                                      BLOCK, 0) != hipSuccess || b <= 0)
       b = 1;
     cached = b;
@@ -78,7 +86,8 @@ hipError_t launch_main(const KArgs& k, hipStream_t st) {
   int64_t grid = (int64_t)per_cu * device_cus();
   const int64_t need = (k.ntiles + 1 + NWAVE - 1) / NWAVE;  // + the scanner wavefront
   if (grid > need) grid = need;
-  hipLaunchKernelGGL((k_intersect_w<MODE, WPPT_SINGLE, CSR>), dim3((unsigned)grid), dim3(BLOCK), 0,
+  hipLaunchKernelGGL((k_intersect_w<MODE, wppt_single<MODE>(), CSR>), dim3((unsigned)grid),
+                     dim3(BLOCK), 0,
                      st, k);
   return hipGetLastError();
 }
@@ -101,7 +110,8 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
   if (v != SPHINT_OK) return v;
   if (!workspace || !aligned256(workspace) || workspace_bytes < sphint_workspace_size(nnz))
     return SPHINT_E_INVAL;
-  const int64_t ntiles = wave_tiles_for(nnz, WPPT_SINGLE);
+  const int64_t ntiles =
+      wave_tiles_for(nnz, mode == SPHINT_EFT_FP64 ? wppt_single<1>() : wppt_single<0>());
   if (ntiles > 0x7fffffffLL) return SPHINT_E_INVAL;
   hipStream_t st = (hipStream_t)stream;
   uint32_t* ws = (uint32_t*)workspace;

@@ -29,7 +29,7 @@
 using namespace sphint;
 
 template <int MODE, int PPT, bool CSR>
-__global__ __launch_bounds__(BLOCK) void k_batch(const KArgs* __restrict__ args,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(const KArgs* __restrict__ args,
                                                  const int64_t* __restrict__ tile_base,
                                                  int n_meshes, int64_t total_tiles) {
   __shared__ WgShared<MODE, PPT, CSR> sh;
@@ -106,10 +106,12 @@ int resident_per_cu_form(sphint_mode mode, int ppt) {
   if (mode == SPHINT_EFT_FP64) {
     if (ppt == 1) return max_resident<1, 1, CSR>();
     if (ppt == 2) return max_resident<1, 2, CSR>();
+    if (ppt == 3) return max_resident<1, 3, CSR>();
     return max_resident<1, 4, CSR>();
   }
   if (ppt == 1) return max_resident<0, 1, CSR>();
   if (ppt == 2) return max_resident<0, 2, CSR>();
+  if (ppt == 3) return max_resident<0, 3, CSR>();
   return max_resident<0, 4, CSR>();
 }
 
@@ -201,6 +203,7 @@ sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
     const bool eft = p->mode == SPHINT_EFT_FP64;
     if (p->ppt == 1) eft ? launch_batch<1, 1>(p, (unsigned)grid, st) : launch_batch<0, 1>(p, (unsigned)grid, st);
     else if (p->ppt == 2) eft ? launch_batch<1, 2>(p, (unsigned)grid, st) : launch_batch<0, 2>(p, (unsigned)grid, st);
+    else if (p->ppt == 3) eft ? launch_batch<1, 3>(p, (unsigned)grid, st) : launch_batch<0, 3>(p, (unsigned)grid, st);
     else eft ? launch_batch<1, 4>(p, (unsigned)grid, st) : launch_batch<0, 4>(p, (unsigned)grid, st);
   }
   if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
@@ -302,7 +305,7 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
         *bar = 0;
         if (key == line) {
           int ppt = 0, wg = -1;
-          if (sscanf(bar + 1, "%d %d", &ppt, &wg) == 2 && (ppt == 1 || ppt == 2 || ppt == 4) &&
+          if (sscanf(bar + 1, "%d %d", &ppt, &wg) == 2 && (ppt >= 1 && ppt <= 4) &&
               wg >= 0) {
             fclose(f);
             p->ppt = ppt;
@@ -326,8 +329,8 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
   hipEvent_t e0 = ev.e0, e1 = ev.e1;
   float best = 1e30f;
   int best_ppt = 1, best_wg = 0;
-  const int ppts[3] = {1, 2, 4};
-  for (int pi = 0; pi < 3; ++pi) {
+  const int ppts[4] = {1, 2, 3, 4};
+  for (int pi = 0; pi < 4; ++pi) {
     const int ppt = ppts[pi];
     const int res = resident_per_cu(p, ppt);
     const int wgs[4] = {res, res > 1 ? res - 1 : 1, res > 2 ? res / 2 : 1, 1};
@@ -375,7 +378,7 @@ extern "C" sphint_status sphint_batch_params(const sphint_plan* p, int* pairs_pe
 
 extern "C" sphint_status sphint_batch_set_params(sphint_plan* p, int pairs_per_thread,
                                                  int wg_per_cu) {
-  if (!p || !(pairs_per_thread == 1 || pairs_per_thread == 2 || pairs_per_thread == 4) ||
+  if (!p || pairs_per_thread < 1 || pairs_per_thread > 4 ||
       wg_per_cu < 0)
     return SPHINT_E_INVAL;
   p->ppt = pairs_per_thread;

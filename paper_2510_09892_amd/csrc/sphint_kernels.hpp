@@ -476,7 +476,7 @@ constexpr int flush_at() {
 // operations per second).  The last wavefront of the grid is the scanner; compute wavefront
 // c of the other W takes tiles c, c + W, c + 2W, ...
 template <int MODE, int WPPT, bool CSR>
-__global__ __launch_bounds__(BLOCK) void k_intersect_w(KArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_intersect_w(KArgs a) {
   __shared__ WgShared<MODE, WPPT, CSR> sh;
   if (threadIdx.x == 0) sh.lock = 0;
   __syncthreads();

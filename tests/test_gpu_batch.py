@@ -102,7 +102,7 @@ def test_batch_equals_per_mesh(torch_cuda, mode, tmp_path):
     ref = per_mesh(torch, devs, mode)
     plan = sphint.BatchPlan(devs, mode=mode)
     try:
-        for ppt in (1, 2, 4):
+        for ppt in (1, 2, 3, 4):
             for wg in (0, 1, 2):
                 note(f"{mode}: params ppt={ppt} wg_per_cu={wg}")
                 plan.set_params(ppt, wg)
@@ -116,7 +116,7 @@ def test_batch_equals_per_mesh(torch_cuda, mode, tmp_path):
         note(f"{mode}: autotune")
         plan.autotune(cache)
         chosen = plan.params()
-        assert chosen[0] in (1, 2, 4) and chosen[1] >= 0
+        assert chosen[0] in (1, 2, 3, 4) and chosen[1] >= 0
         assert os.path.exists(cache) and open(cache).read().strip()
         plan.set_params(1, 1)
         plan.autotune(cache)  # read back from the cache
