@@ -197,3 +197,22 @@ def test_exact_sign_matches_oracle(hc):
             Xv, Yv, Zv = t[X], t[Y], t[Z]
             want = sg(t["Z0"] ** 2 * (Xv * Xv + Yv * Yv + Zv * Zv) - (Zv * Zv << (2 * K)))
             assert hc.sphint_hostcheck_exact_sign(which, *v) == want, (which, v)
+
+
+def test_eft_heights_near_pole_within_ulps(hc):
+    """Latitudes a few ulps from an endpoint's height near a pole: the first height filter
+    leaves these open and the second must decide them correctly (or hand them on)."""
+    P = inputs.ill_conditioned(3000, seed_tag=48)
+    rows = []
+    for i in np.flatnonzero(P.part == 2)[:300]:
+        x1 = tuple(float(v) for v in P.p1[i])
+        zh = x1[2] / math.sqrt(x1[0] ** 2 + x1[1] ** 2 + x1[2] ** 2)
+        z0 = zh
+        for _ in range(4):
+            z0 = math.nextafter(z0, -2.0)
+        for _ in range(9):
+            rows.append((*x1, *P.p2[i], z0))
+            z0 = math.nextafter(z0, 2.0)
+    a = np.array(rows)
+    soa = [a[:, k].copy() for k in range(7)]
+    compare_eft(hc, soa)
