@@ -35,7 +35,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   __shared__ WgShared<MODE, PPT, CSR> sh;
   if (threadIdx.x == 0) sh.lock = 0;
   __syncthreads();
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
   const int64_t gw = (int64_t)blockIdx.x * NWAVE + wave;
   const int64_t W = (int64_t)gridDim.x * NWAVE - 1;
   if (gw == W) {  // the scanner follows the global tile order: mesh after mesh

@@ -250,14 +250,16 @@ struct TileRegs {
   int agg;
 };
 
-// Inputs of one row (64 pairs, one per lane) of a tile.
+// Inputs of one row (64 pairs, one per lane) of a tile; `o` is the pair's offset in the
+// tile (the pair is tile base + o).
 struct RowIn {
   double x1, y1, z1, x2, y2, z2, z0;
-  int64_t i;
+  uint32_t o;
   bool valid;
 };
 
-// Per-tile context for loading rows: the tile's first pair.
+// Per-tile context for loading rows: the tile's first pair (wavefront-uniform, so that
+// per-tile array bases live in scalar registers and lanes add 32-bit offsets).
 struct TileCtx {
   int64_t base;
 };
@@ -277,22 +279,26 @@ __device__ __forceinline__ TileCtx tile_ctx(const KArgs& a, int64_t tile) {
 template <bool CSR>
 __device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int j) {
   RowIn r;
-  r.i = c.base + (int64_t)j * 64 + __lane_id();
-  r.valid = r.i < a.nnz;
-  const int64_t ii = r.valid ? r.i : a.nnz - 1;
-  int64_t arc = ii;
+  // offsets stay below 1024 (a tile has at most 1024 pairs); the mask tells the compiler
+  // so, which lets it address from a scalar base plus a 32-bit lane offset
+  r.o = (uint32_t)(j * 64 + __lane_id()) & 1023u;
+  r.valid = c.base + (int64_t)r.o < a.nnz;
+  const uint32_t oc = (r.valid ? r.o : (uint32_t)(a.nnz - 1 - c.base)) & 1023u;
   if (CSR) {
-    const int64_t pa = (int64_t)gptr(a.parc)[ii];
-    arc = pa < a.n_arcs ? pa : a.n_arcs - 1;
-    const int32_t li = gptr(a.idx)[ii];
+    const int64_t pa = (int64_t)gptr(a.parc + c.base)[oc];
+    const int64_t arc = pa < a.n_arcs ? pa : a.n_arcs - 1;
+    const int32_t li = gptr(a.idx + c.base)[oc];
     const bool ok = li >= 0 && li < a.n_lat;
     const double z = gptr(a.lat_z)[ok ? li : 0];
     r.z0 = ok ? z : __builtin_nan("");
+    r.x1 = gptr(a.x1)[arc]; r.y1 = gptr(a.y1)[arc]; r.z1 = gptr(a.z1)[arc];
+    r.x2 = gptr(a.x2)[arc]; r.y2 = gptr(a.y2)[arc]; r.z2 = gptr(a.z2)[arc];
   } else {
-    r.z0 = gptr(a.lat_z)[ii];
+    r.z0 = gptr(a.lat_z + c.base)[oc];
+    r.x1 = gptr(a.x1 + c.base)[oc]; r.y1 = gptr(a.y1 + c.base)[oc];
+    r.z1 = gptr(a.z1 + c.base)[oc]; r.x2 = gptr(a.x2 + c.base)[oc];
+    r.y2 = gptr(a.y2 + c.base)[oc]; r.z2 = gptr(a.z2 + c.base)[oc];
   }
-  r.x1 = gptr(a.x1)[arc]; r.y1 = gptr(a.y1)[arc]; r.z1 = gptr(a.z1)[arc];
-  r.x2 = gptr(a.x2)[arc]; r.y2 = gptr(a.y2)[arc]; r.z2 = gptr(a.z2)[arc];
   return r;
 }
 
@@ -313,8 +319,8 @@ __device__ __forceinline__ void fill_pair_arcs(const int64_t* __restrict__ off, 
 // Evaluates one row already loaded, writes its counts and flags, and accumulates the
 // tile's in-order hit offsets.
 template <int MODE, int WPPT, class Shared>
-__device__ __forceinline__ void eval_row(const KArgs& a, const RowIn& in, int j, TileRegs<WPPT>& r,
-                                         Shared& sh) {
+__device__ __forceinline__ void eval_row(const KArgs& a, const TileCtx& c, const RowIn& in, int j,
+                                         TileRegs<WPPT>& r, Shared& sh) {
   const int lane = __lane_id();
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   PairOut& o = r.o[j];
@@ -334,8 +340,8 @@ __device__ __forceinline__ void eval_row(const KArgs& a, const RowIn& in, int j,
   const int cnt = in.valid ? o.count : 0;
   o.count = cnt;
   if (in.valid) {
-    gptr(a.ocount)[in.i] = (uint8_t)cnt;
-    if (a.oflags) gptr(a.oflags)[in.i] = (uint8_t)o.flags;
+    gptr(a.ocount + c.base)[in.o] = (uint8_t)cnt;
+    if (a.oflags) gptr(a.oflags + c.base)[in.o] = (uint8_t)o.flags;
   }
   const unsigned long long b1 = __ballot(cnt >= 1);
   const unsigned long long b2 = __ballot(cnt >= 2);
@@ -372,14 +378,19 @@ __device__ __forceinline__ void flush_tile(const KArgs& a, int64_t tile, int cou
   const int lane = __lane_id();
   const int64_t base = tile * (int64_t)(64 * WPPT);
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int k = lane; k < count; k += 64) {
-    const int64_t pos = prefix + k;
-    if (pos < a.cap) {
-      gptr(a.ox)[pos] = st.x[k];
-      gptr(a.oy)[pos] = st.y[k];
-      gptr(a.opair)[pos] = base + st.pair[k];
-      gptr(a.oroot)[pos] = st.root[k];
-    }
+  // hits [prefix, prefix + count) clipped to the capacity, from uniform bases
+  const int64_t room = a.cap - prefix;
+  const int n = room <= 0 ? 0 : (room < count ? (int)room : count);
+  double* ox = a.ox + prefix;
+  double* oy = a.oy + prefix;
+  int64_t* op = a.opair + prefix;
+  uint8_t* orr = a.oroot + prefix;
+  for (int k = lane; k < n; k += 64) {  // k < 2 * 64 * WPPT <= 2048
+    const uint32_t kk = (uint32_t)k & 2047u;
+    gptr(ox)[kk] = st.x[kk];
+    gptr(oy)[kk] = st.y[kk];
+    gptr(op)[kk] = base + st.pair[kk];
+    gptr(orr)[kk] = st.root[kk];
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -396,7 +407,8 @@ template <int MODE, int WPPT, bool CSR, int FLUSH_AT, class Next>
 __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT, CSR>& sh,
                                           Next&& next) {
   static_assert(FLUSH_AT >= 1 && FLUSH_AT <= WPPT, "flush point inside the tile");
-  const int wave = threadIdx.x >> 6;
+  static_assert(WPPT <= 16, "pair and hit offsets within a tile are masked to 10 and 11 bits");
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
   WaveStage<WPPT>& st = sh.stage[wave];
   bool pending = false;
   int pm = 0, pagg = 0;
@@ -427,7 +439,7 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
         ctx2 = tile_ctx<WPPT, CSR>(args[m2], tile2);
         nxt = load_row<CSR>(args[m2], ctx2, 0);
       }
-      eval_row<MODE, WPPT>(a, cur, j, r, sh);
+      eval_row<MODE, WPPT>(a, ctx, cur, j, r, sh);
       if (j + 1 == FLUSH_AT) {
         if (pending) {
           const KArgs& pa = args[pm];
@@ -480,7 +492,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   __shared__ WgShared<MODE, WPPT, CSR> sh;
   if (threadIdx.x == 0) sh.lock = 0;
   __syncthreads();
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
   const int64_t gw = (int64_t)blockIdx.x * NWAVE + wave;
   const int64_t W = (int64_t)gridDim.x * NWAVE - 1;
   if (gw == W) {
