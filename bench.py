@@ -133,8 +133,10 @@ def pctl(v):
     return [v[int(q * (len(v) - 1))] for q in (0.1, 0.5, 0.9)]
 
 
-def latency_small(torch, sphint, inputs, reps=200):
-    """Per-call latency on the 1e5-arc uniform workload (host enqueue to completion)."""
+def latency_small(torch, sphint, inputs, reps=1000):
+    """The 1e5-arc uniform workload (EFT): per-call latency, host enqueue to completion, and
+    the throughput of back-to-back replays of the call captured in a hipGraph (a one-mesh
+    batched plan)."""
     P = inputs.uniform_arcs(100_000, seed_tag=0)
     dev = [torch.from_numpy(a).cuda() for a in P.soa()]
     out = sphint.Output(len(P))
@@ -147,7 +149,21 @@ def latency_small(torch, sphint, inputs, reps=200):
         if r >= 10:
             lat.append((time.perf_counter() - t0) * 1e6)
     lat.sort()
-    return dict(p50_us=lat[len(lat) // 2], p99_us=lat[int(len(lat) * 0.99) - 1], calls=reps)
+    plan = sphint.BatchPlan([dict(p1=tuple(dev[:3]), p2=tuple(dev[3:6]), lat_z=dev[6], out=out)],
+                            mode="eft")
+    for _ in range(10):
+        plan.launch()
+    torch.cuda.synchronize()
+    n_rep = 200
+    t0 = time.perf_counter()
+    for _ in range(n_rep):
+        plan.launch()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n_rep
+    plan.check()
+    plan.close()
+    return dict(p50_us=lat[len(lat) // 2], p99_us=lat[int(len(lat) * 0.99) - 1], calls=reps,
+                graph_replay_us=dt * 1e6, graph_replay_pairs_per_s=len(P) / dt)
 
 
 def serving(torch, args, log):

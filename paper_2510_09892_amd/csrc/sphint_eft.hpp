@@ -55,9 +55,10 @@ __host__ __device__ __forceinline__ dop3 accu_dop(double a, double b, double c, 
   return {n.hi, n.lo, __builtin_fabs(p1.hi) + __builtin_fabs(p2.hi)};
 }
 
-// Alg. 6 (SumNonNeg).
+// Alg. 6 (SumNonNeg).  Its leading TwoSum adds two non-negative numbers, so it is done as
+// FastTwoSum(max, min): both are exact, so the pair is the same, in fewer dependent steps.
 __host__ __device__ __forceinline__ dd sum_non_neg(dd A, dd B) {
-  dd H = two_sum(A.hi, B.hi);
+  dd H = fast_two_sum(__builtin_fmax(A.hi, B.hi), __builtin_fmin(A.hi, B.hi));
   double c = A.lo + B.lo;
   double d = H.lo + c;
   return fast_two_sum(H.hi, d);

@@ -246,20 +246,23 @@ struct S2Eft {
 // from Alg. 7 (<= 11 u^2 S2 and 14 u^2 S3 over the renormalised normal), the normal error
 // (3.01 u^2 m_i per component), CompDotC over four terms (Eq. 5.1, 16 u^2 S3 z0^2) and the
 // compensation sum.  The filter uses 2^-96 = 1024 u^2 per term: a factor >= 25 of margin.
+// Alg. 1's TwoSums run here as FastTwoSum: after the leading product S3 C, every term is at
+// most about u times the running sum (|C_lo| <= u C, |s3| <= u S3), so FastTwoSum's
+// precondition holds and, both being exact, it returns TwoSum's pair.
 __host__ __device__ __forceinline__ S2Eft s2_eft(const ArcEft& a, double z0) {
   dd C = two_prod(z0, z0);
   dd p = two_prod(a.S3, C.hi);  // Alg. 1 over {S3, S3, s3, s3} . {C, eC, C, eC}
   double ph = p.hi, s = p.lo;
   dd h = two_prod(a.S3, C.lo);
-  dd q = two_sum(ph, h.hi);
+  dd q = fast_two_sum(ph, h.hi);
   ph = q.hi;
   s = s + (q.lo + h.lo);
   h = two_prod(a.s3, C.hi);
-  q = two_sum(ph, h.hi);
+  q = fast_two_sum(ph, h.hi);
   ph = q.hi;
   s = s + (q.lo + h.lo);
   h = two_prod(a.s3, C.lo);
-  q = two_sum(ph, h.hi);
+  q = fast_two_sum(ph, h.hi);
   ph = q.hi;
   s = s + (q.lo + h.lo);
   dd E = two_sum(a.S2, -ph);
@@ -310,8 +313,10 @@ struct CdState {
   double p, s;
 };
 
+// The second term is e_F z0 with |e_F| <= 3.01 u |F| (F's pair comes from a TwoProduct and
+// two products of renormalised parts), so FastTwoSum returns TwoSum's exact pair.
 __host__ __device__ __forceinline__ CdState comp_dot_head(dd t0, dd t1) {
-  const dd q = two_sum(t0.hi, t1.hi);
+  const dd q = fast_two_sum(t0.hi, t1.hi);
   return {q.hi, t0.lo + (q.lo + t1.lo)};
 }
 

@@ -153,3 +153,34 @@ def test_batch_small_mesh_against_oracle(torch_cuda):
             np.testing.assert_array_equal(r["pair"], np.array(ex.hit_pair, dtype=np.int64))
     finally:
         plan.close()
+
+
+def test_batch_dense_meshes(torch_cuda):
+    """Dense (1:1) meshes in one plan equal per-mesh dense calls."""
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    sets = [inputs.ill_conditioned(n, seed_tag=42 + k) for k, n in enumerate((700, 20_000, 5_001))]
+    devs = []
+    for P in sets:
+        d = [torch.from_numpy(a).cuda() for a in P.soa()]
+        devs.append(dict(p1=tuple(d[:3]), p2=tuple(d[3:6]), lat_z=d[6], out=sphint.Output(len(P))))
+    ref = []
+    for d in devs:
+        o = sphint.Output(d["out"].nnz)
+        sphint.arc_constlat(d["p1"], d["p2"], d["lat_z"], mode="eft", out=o)
+        torch.cuda.synchronize()
+        o.check()
+        ref.append(read(o))
+    plan = sphint.BatchPlan(devs, mode="eft")
+    try:
+        for ppt in (1, 3, 4):
+            note(f"dense batch ppt={ppt}")
+            plan.set_params(ppt, 0)
+            scrub(torch, devs)
+            plan.launch()
+            torch.cuda.synchronize()
+            plan.check()
+            for d, r in zip(devs, ref):
+                assert same(read(d["out"]), r), ppt
+    finally:
+        plan.close()
