@@ -191,8 +191,19 @@ def serving(torch, args, log):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(P, inputs, sample):
-    """The oracle (exact predicates + 100-digit points) on a stratified sample, all workers."""
+    """The oracle (exact predicates + 100-digit points) on a stratified sample, all workers,
+    plus one in-process worker on a tenth of it."""
     from oracle import batch as OB
     idx = inputs.stratified_sample(P, sample // 3, seed=11)
     S = P.take(idx)
@@ -200,9 +211,52 @@ def cpu_baseline(P, inputs, sample):
     t0 = time.perf_counter()
     OB.exact(*S.soa(), workers=workers)
     dt = time.perf_counter() - t0
+    S1 = P.take(idx[::10])
+    t1 = time.perf_counter()
+    OB.exact(*S1.soa(), workers=1)
+    d1 = time.perf_counter() - t1
     return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "kind": "oracle",
             "sample": f"{len(S)} pairs, stratified over the 3 parts of the same workload "
-                      f"(exact integer predicates + 100-digit decimal points), {dt:.1f} s wall"}
+                      f"(exact integer predicates + 100-digit decimal points), {dt:.1f} s wall",
+            "single_core_value": len(S1) / d1, "cpu_model": cpu_model()}
+
+
+def cpu_replica(P, sample, threads):
+    """Context only: the library's own per-pair arithmetic compiled for the host (the CPU
+    check library, one evaluation per pair, exact fallbacks inline), on `threads` host
+    threads (ctypes releases the GIL), over the first `sample` pairs of each part."""
+    import ctypes
+    import threading
+    import numpy as np
+    path = os.path.join(ROOT, "paper_2510_09892_amd", "libsphint_hostcheck.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    lib.sphint_hostcheck_eval.argtypes = [ctypes.c_int, ctypes.c_int64] + [dp] * 7 + [ip] * 4 + [dp] * 4
+    idx = np.concatenate([np.flatnonzero(P.part == k)[: sample // 3] for k in range(3)])
+    soa = [np.ascontiguousarray(a[idx]) for a in P.soa()]
+    n = len(idx)
+    out = {"threads": threads, "pairs": n, "unit": "intersections/s", "cpu_model": cpu_model(),
+           "kind": "host build of the kernel arithmetic (not the oracle)"}
+    for mode, name in ((1, "eft"), (0, "naive")):
+        ints = [np.zeros(n, np.int32) for _ in range(4)]
+        dbl = [np.zeros(n, np.float64) for _ in range(4)]
+        bounds = np.linspace(0, n, threads + 1).astype(np.int64)
+
+        def work(lo, hi):
+            off = lambda a: a[lo:hi].ctypes.data_as(ctypes.POINTER(
+                ctypes.c_double if a.dtype == np.float64 else ctypes.c_int32))
+            lib.sphint_hostcheck_eval(mode, int(hi - lo), *[off(a) for a in soa],
+                                      *[off(a) for a in ints], *[off(a) for a in dbl])
+        ts = [threading.Thread(target=work, args=(bounds[k], bounds[k + 1])) for k in range(threads)]
+        t0 = time.perf_counter()
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        out[name] = n / (time.perf_counter() - t0)
+    return out
 
 
 def cpu_baseline_csr(meshes, inputs, sample):
@@ -277,11 +331,12 @@ def main():
         workload = ("1e7 ill-conditioned arcs in three parts (short 1e-10..1e-6 rad; "
                     "near-tangent r<=1e-12; within 1e-6 rad of a pole), one latitude "
                     "per arc, dense 1:1, mode ")
-    cpu = None
+    cpu = replica = None
     if not args.no_cpu_baseline:
         # before any GPU call: the oracle's worker processes are forked from this one
         log(f"[bench] cpu baseline: oracle on {args.cpu_sample} pairs")
         if P is not None:
+            replica = cpu_replica(P, 3_000_000, min(os.cpu_count() or 1, 16))
             cpu = cpu_baseline(P, inputs, args.cpu_sample)
         else:
             cpu = cpu_baseline_csr([mesh], inputs, args.cpu_sample)
@@ -360,6 +415,8 @@ def main():
         line["latency_1e5"] = latency_small(torch, sphint, inputs)
     if not args.no_serve and args.workload == "ill1e7":
         line["serving"] = serving(torch, args, log)
+    if replica is not None:
+        line["cpu_replica"] = replica
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

@@ -108,7 +108,9 @@ class Server:
     # -- arena management (only free slots are touched: nothing of theirs is in flight)
     def _fit(self, free, need):
         """A free slot whose arena holds `need` bytes, growing one within the budget if
-        necessary (releasing idle arenas of other free slots first); None if none can."""
+        necessary (releasing idle arenas of other free slots first); None if none can.
+        The budget bounds the bytes the slots' arenas hold; memory of a released arena
+        stays in PyTorch's cache and serves the next arena."""
         ok = [s for s in free if s.capacity >= need]
         if ok:
             return min(ok, key=lambda s: s.capacity)
@@ -123,8 +125,9 @@ class Server:
                 return None
         self.reserved -= s.capacity
         s.arena = None
-        with self.torch.cuda.stream(s.stream):
-            s.arena = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        # allocated on the device's default stream, so that a released arena's memory is
+        # reusable by every slot (only idle slots' arenas are ever released or replaced)
+        s.arena = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
         s.capacity = need
         self.reserved += need
         return s
