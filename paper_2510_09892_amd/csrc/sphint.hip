@@ -13,9 +13,11 @@ using namespace sphint;
 
 namespace {
 
-// Clears the tile states, counter and error word; writes *ototal = 0 for empty calls.
+// Clears the tile states, counter and error word; writes *ototal = 0 for empty calls; for
+// CSR calls (off != NULL) also writes the pair-to-arc table (one launch for both).
 __global__ void k_init(uint32_t* ws, uint64_t* status, int64_t ntiles, int64_t* ototal,
-                       int64_t nnz) {
+                       int64_t nnz, const int64_t* __restrict__ off, int64_t n_arcs,
+                       uint32_t* __restrict__ parc) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     ws[0] = 0u;
@@ -23,6 +25,10 @@ __global__ void k_init(uint32_t* ws, uint64_t* status, int64_t ntiles, int64_t* 
     if (nnz == 0) *ototal = 0;
   }
   for (int64_t k = t; k < ntiles; k += (int64_t)gridDim.x * blockDim.x) status[k] = 0ull;
+  if (off && nnz > 0)
+    fill_pair_arcs(off, n_arcs, nnz, parc,
+                   (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6),
+                   (int64_t)gridDim.x * (blockDim.x / 64));
 }
 
 }  // namespace
@@ -30,8 +36,8 @@ __global__ void k_init(uint32_t* ws, uint64_t* status, int64_t ntiles, int64_t* 
 namespace sphint {
 __global__ void k_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs, int64_t nnz,
                             uint32_t* __restrict__ parc) {
-  fill_pair_arcs(off, n_arcs, nnz, parc, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
-                 (int64_t)gridDim.x * blockDim.x);
+  fill_pair_arcs(off, n_arcs, nnz, parc, (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6),
+                 (int64_t)gridDim.x * (blockDim.x / 64));
 }
 }  // namespace sphint
 
@@ -119,19 +125,18 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
 
   LaunchChain chain;
   if (chain.begin(st) != hipSuccess) return SPHINT_E_HIP;
+  uint32_t* parc = (uint32_t*)((char*)workspace + WS_HEADER + 8 * status_words_for(nnz));
   int64_t init_threads = ntiles > 0 ? ntiles : 1;
-  unsigned init_blocks = (unsigned)((init_threads + 255) / 256);
-  if (init_blocks > 1024) init_blocks = 1024;
-  hipLaunchKernelGGL(k_init, dim3(init_blocks), dim3(256), 0, st, ws, status, ntiles, out_total,
-                     nnz);
+  if (lat_offsets && n_arcs > init_threads) init_threads = n_arcs;  // one lane per arc
+  int64_t init_blocks = (init_threads + 255) / 256;
+  if (init_blocks > 8192) init_blocks = 8192;
+  hipLaunchKernelGGL(k_init, dim3((unsigned)init_blocks), dim3(256), 0, st, ws, status, ntiles,
+                     out_total, nnz, lat_offsets, n_arcs, parc);
   if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
   if (nnz == 0) return chain.end() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
 
-  uint32_t* parc = (uint32_t*)((char*)workspace + WS_HEADER + 8 * status_words_for(nnz));
   KArgs k = make_args(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out, out_count,
                       out_flags, out_total, ws, status, ntiles, parc);
-  if (lat_offsets && launch_pair_arcs(lat_offsets, n_arcs, nnz, parc, st) != hipSuccess)
-    return SPHINT_E_HIP;
   if (prof_start && hipEventRecord(prof_start, st) != hipSuccess) return SPHINT_E_HIP;
   const bool csr = lat_offsets != nullptr;
   hipError_t e;

@@ -302,17 +302,37 @@ __device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int 
   return r;
 }
 
-// CSR pair-to-arc table: parc[k] = the arc owning entry k, for the arcs [a_begin, a_end)
-// handled by this launch (one thread per arc, grid-stride; offsets read once, coalesced).
-// Entries are written only inside [0, nnz).
+// CSR pair-to-arc table: parc[k] = the arc owning entry k.  Wavefront w of nw takes 64
+// consecutive arcs at a time (their offsets read once, coalesced).  The entries of those
+// arcs form one run, which the 64 lanes write together (coalesced): each entry finds its
+// arc by a binary search over the 64 arcs' first entries, held one per lane.  Entries are
+// written only inside [0, nnz) and only by the arc whose range holds them, so malformed
+// offsets leave entries unwritten (clamped where they are read) but never write out of
+// bounds.
 __device__ __forceinline__ void fill_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs,
                                                int64_t nnz, uint32_t* __restrict__ parc,
-                                               int64_t a, int64_t stride) {
-  for (; a < n_arcs; a += stride) {
-    int64_t b = off[a], e = off[a + 1];
-    b = b > 0 ? b : 0;
-    e = e < nnz ? e : nnz;
-    for (int64_t q = b; q < e; ++q) parc[q] = (uint32_t)a;
+                                               int64_t w, int64_t nw) {
+  const int lane = __lane_id();
+  for (int64_t a0 = w * 64; a0 < n_arcs; a0 += nw * 64) {  // wavefront-uniform loop
+    const int64_t a = a0 + lane;
+    const bool ok = a < n_arcs;
+    int64_t b = ok ? off[a] : nnz, e = ok ? off[a + 1] : nnz;
+    b = b < 0 ? 0 : (b > nnz ? nnz : b);
+    e = e < b ? b : (e > nnz ? nnz : e);
+    const int last = n_arcs - a0 < 64 ? (int)(n_arcs - a0) - 1 : 63;
+    const int64_t lo = __shfl(b, 0, 64);
+    const int64_t hi = __shfl(e, last, 64);
+    for (int64_t q0 = lo; q0 < hi; q0 += 64) {
+      const int64_t q = q0 + lane;
+      int l = 0;  // largest lane with b <= q (lane 0's b = lo <= q)
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int64_t bc = __shfl(b, l + step, 64);
+        if (bc <= q) l += step;
+      }
+      const int64_t el = __shfl(e, l, 64);
+      if (q < hi && q < el) parc[q] = (uint32_t)(a0 + l);
+    }
   }
 }
 
