@@ -191,6 +191,25 @@ def serving(torch, args, log):
     return out
 
 
+def candidate_timing(torch, sphint, inputs, mesh, dp, lz, reps=10):
+    """CSR candidate lists of the mesh built on the GPU (sphint_candidates_count + _fill,
+    including the host read of nnz between them) against the host generator."""
+    t0 = time.perf_counter()
+    off_h, idx_h = inputs.candidates(mesh.p1, mesh.p2, mesh.lat_z)
+    host_s = time.perf_counter() - t0
+    for _ in range(2):
+        sphint.candidates(tuple(dp[:3]), tuple(dp[3:]), lz, 1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        off, idx = sphint.candidates(tuple(dp[:3]), tuple(dp[3:]), lz, 1e-12)
+    torch.cuda.synchronize()
+    gpu_s = (time.perf_counter() - t0) / reps
+    return {"gpu_ms": gpu_s * 1e3, "host_numpy_s": host_s, "arcs": len(mesh.p1),
+            "candidates_gpu": int(len(idx)), "candidates_host": int(len(idx_h)),
+            "arcs_per_s_gpu": len(mesh.p1) / gpu_s}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -415,6 +434,9 @@ def main():
         line["latency_1e5"] = latency_small(torch, sphint, inputs)
     if not args.no_serve and args.workload == "ill1e7":
         line["serving"] = serving(torch, args, log)
+    if args.workload == "cubed1024":
+        log("[bench] candidate lists on the GPU and on the host")
+        line["candidates"] = candidate_timing(torch, sphint, inputs, mesh, dp, lz)
     if replica is not None:
         line["cpu_replica"] = replica
     if cpu is not None:

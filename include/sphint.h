@@ -187,6 +187,39 @@ sphint_status sphint_batch_set_params(sphint_plan *plan, int pairs_per_thread, i
 sphint_status sphint_batch_check(const sphint_plan *plan);
 void sphint_plan_destroy(sphint_plan *plan);
 
+/* ------------------------------------------------------------ candidate lists (CSR) */
+
+/*
+ * The step before the intersection path: each arc's candidate latitudes, as the CSR lists
+ * sphint_arc_constlat takes.  lat_z (n_lat < 2^31 entries, device) must be ascending.  Arc
+ * i's candidates are the latitudes in [lo_i - pad - 2^-46, hi_i + pad + 2^-46], where
+ * [lo_i, hi_i] is the height range the minor arc covers (Sec. 2's containment rule read as a
+ * range query: the heights of the normalised endpoints, extended to the top or bottom of the
+ * great circle when the slope signs at the endpoints put it inside the arc, an uncertified
+ * sign counting as both), computed in binary64; the 2^-46 covers the rounding of those
+ * bounds, so every latitude the arc meets is a candidate.  Arcs with a non-finite
+ * coordinate get none.  pad >= 0.
+ *
+ * Two calls, in order on one stream with one workspace of at least
+ * sphint_candidates_workspace_size(n_arcs) bytes (256-byte aligned):
+ *   sphint_candidates_count writes lat_offsets[0..n_arcs] (device int64; lat_offsets[0] = 0,
+ *     lat_offsets[n_arcs] = nnz) and *out_nnz (device int64), and keeps each arc's first
+ *     candidate and count in the workspace;
+ *   sphint_candidates_fill then writes lat_idx[0..min(nnz, capacity)) (device int32): the
+ *     candidates of arc i, ascending, at [lat_offsets[i], lat_offsets[i+1]).  A caller that
+ *     does not know nnz reads *out_nnz after the first call (or passes an upper bound).
+ * SPHINT_E_INVAL (no launch) for negative sizes, missing pointers, a short or misaligned
+ * workspace or a negative pad; SPHINT_E_HIP if a launch fails.
+ */
+size_t sphint_candidates_workspace_size(int64_t n_arcs);
+sphint_status sphint_candidates_count(int64_t n_arcs, sphint_pts_soa p1, sphint_pts_soa p2,
+                                      const double *lat_z, int64_t n_lat, double pad,
+                                      int64_t *lat_offsets, int64_t *out_nnz, void *workspace,
+                                      size_t workspace_bytes, void *stream);
+sphint_status sphint_candidates_fill(int64_t n_arcs, const int64_t *lat_offsets,
+                                     int32_t *lat_idx, int64_t capacity, void *workspace,
+                                     size_t workspace_bytes, void *stream);
+
 const char *sphint_status_string(sphint_status s);
 /* "sphint <version> gfx950" */
 const char *sphint_version(void);

@@ -3,6 +3,7 @@
 // the same header the kernels use, so the CPU tests exercise the exact operation sequence
 // of the GPU evaluation; undecided predicates are resolved immediately instead of one lane
 // at a time.
+#include "sphint_cand.hpp"
 #include "sphint_pair.hpp"
 
 extern "C" int sphint_hostcheck_eval(int mode, int64_t n, const double* x1, const double* y1,
@@ -38,4 +39,15 @@ extern "C" int sphint_hostcheck_exact_sign(int which, double x1, double y1, doub
                                            double y2, double z2, double z0) {
   static thread_local double arena[sphint::xp::ARENA];
   return sphint::exact_sign(which, x1, y1, z1, x2, y2, z2, z0, arena);
+}
+
+// Candidate latitudes of each arc (first index and count in the ascending table lat_z).
+extern "C" int sphint_hostcheck_candidates(int64_t n, const double* x1, const double* y1,
+                                           const double* z1, const double* x2, const double* y2,
+                                           const double* z2, const double* lat_z, int32_t n_lat,
+                                           double pad, int32_t* first, int32_t* count) {
+  for (int64_t i = 0; i < n; ++i)
+    sphint::arc_candidates(x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], lat_z, n_lat, pad, first[i],
+                           count[i]);
+  return 0;
 }

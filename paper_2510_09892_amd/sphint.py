@@ -27,6 +27,8 @@ EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_batch_plan_create", "sphint_batch_autotune", "sphint_batch_launch",
            "sphint_batch_params", "sphint_batch_set_params", "sphint_batch_check",
            "sphint_plan_destroy",
+           "sphint_candidates_workspace_size", "sphint_candidates_count",
+           "sphint_candidates_fill",
            "sphint_status_string",
            "sphint_version")
 
@@ -87,6 +89,13 @@ def load():
     lib.sphint_batch_set_params.restype = ctypes.c_int
     lib.sphint_batch_check.argtypes = [vp]
     lib.sphint_batch_check.restype = ctypes.c_int
+    lib.sphint_candidates_workspace_size.argtypes = [i64]
+    lib.sphint_candidates_workspace_size.restype = sz
+    lib.sphint_candidates_count.argtypes = [i64, PtsSoA, PtsSoA, vp, i64, ctypes.c_double, vp, vp,
+                                            vp, sz, vp]
+    lib.sphint_candidates_count.restype = ctypes.c_int
+    lib.sphint_candidates_fill.argtypes = [i64, vp, vp, i64, vp, sz, vp]
+    lib.sphint_candidates_fill.restype = ctypes.c_int
     lib.sphint_plan_destroy.argtypes = [vp]
     lib.sphint_plan_destroy.restype = None
     lib.sphint_status_string.argtypes = [ctypes.c_int]
@@ -196,6 +205,35 @@ def arc_constlat(p1, p2, lat_z, lat_offsets=None, lat_idx=None, mode="eft", out=
                                  _ptr(out.workspace), out.ws_bytes, _stream(stream))
     _check(st, "sphint_arc_constlat")
     return out
+
+
+def candidates(p1, p2, lat_z, pad=0.0, stream=None):
+    """CSR candidate lists on the GPU (sphint_candidates_count, then _fill): returns
+    (lat_offsets int64 [n_arcs + 1], lat_idx int32 [nnz]) device tensors.  lat_z must be
+    ascending.  Synchronises once, to read nnz."""
+    import torch
+    lib = load()
+    s1, n_arcs = _soa(p1)
+    s2, n2 = _soa(p2)
+    if n2 != n_arcs:
+        raise SphintError("p1 and p2 differ in length")
+    if lat_z.dtype != torch.float64 or not lat_z.is_cuda:
+        raise SphintError("lat_z must be a float64 CUDA tensor")
+    dev = lat_z.device
+    wsb = int(lib.sphint_candidates_workspace_size(n_arcs))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    off = torch.empty(n_arcs + 1, dtype=torch.int64, device=dev)
+    nnz = torch.zeros(1, dtype=torch.int64, device=dev)
+    st = _stream(stream)
+    _check(lib.sphint_candidates_count(n_arcs, s1, s2, _ptr(lat_z), len(lat_z), float(pad),
+                                       _ptr(off), _ptr(nnz), _ptr(ws), wsb, st),
+           "sphint_candidates_count")
+    (torch.cuda.current_stream(dev) if stream is None else stream).synchronize()
+    n = int(nnz.item())
+    idx = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    _check(lib.sphint_candidates_fill(n_arcs, _ptr(off), _ptr(idx), n, _ptr(ws), wsb, st),
+           "sphint_candidates_fill")
+    return off, idx[:n]
 
 
 def arc_constlat_raw(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, hits, count,
