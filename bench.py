@@ -128,6 +128,18 @@ def roofline(mode, r, pairs, bytes_launch, kernel, tag):
     return roof
 
 
+def copy_calibration(torch, nbytes):
+    """A plain device copy of known size, for scaling the profiler's byte counters."""
+    if not nbytes:
+        return
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: {nbytes} bytes x3")
+
+
 def pctl(v):
     v = sorted(v)
     return [v[int(q * (len(v) - 1))] for q in (0.1, 0.5, 0.9)]
@@ -310,9 +322,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000)
-    ap.add_argument("--workload", default="ill1e7", choices=["ill1e7", "cubed1024", "batch64"],
+    ap.add_argument("--workload", default="ill1e7",
+                    choices=["ill1e7", "cubed1024", "batch64", "arcarc1e7"],
                     help="ill1e7: the headline (1e7 ill-conditioned dense pairs); cubed1024: "
-                         "regridding-shaped CSR; batch64: 64 uneven meshes in one launch")
+                         "regridding-shaped CSR; batch64: 64 uneven meshes in one launch; "
+                         "arcarc1e7: 1e7 arc x arc pairs")
     ap.add_argument("--modes", default="eft,naive")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -336,6 +350,8 @@ def main():
     sphint.load()
     if args.workload == "batch64":
         return bench_batch(args, torch, np, inputs, sphint)
+    if args.workload == "arcarc1e7":
+        return bench_arcarc(args, torch, np, inputs, sphint)
     if args.workload == "cubed1024":
         log("[bench] generating the ne=1024 cubed sphere x 1800 latitudes")
         mesh = inputs.cubed_sphere(1024)
@@ -386,13 +402,7 @@ def main():
         log(f"[bench] mode={mode} wall={r['wall_s']:.4f}s kernel_mean={statistics.mean(r['kernel_ms']):.4f}ms "
             f"hits={r['total']}")
 
-    if args.copy_calibration:
-        src = torch.empty(args.copy_calibration // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] copy calibration: {args.copy_calibration} bytes x3")
+    copy_calibration(torch, args.copy_calibration)
 
     head = "eft" if "eft" in res else next(iter(res))
     r = res[head]
@@ -511,6 +521,170 @@ def bench_batch(args, torch, np, inputs, sphint):
                    "pairs": nnz, "hits": r["hits"]},
         "batch": res,
     }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+# Arc x arc: per pair, four endpoints read (12 binary64) and the point, count and flags
+# written.  Operations as counted for the latitude path: EFT normals (two AccuDOP cross
+# products, TwoSum-renormalised: 114) and the first filter stage of four orientations (60)
+# per pair; per hit three eight-term CompDots, SumOfSquares, sqrt, three divisions and the
+# sign (254).  Naive: two cross products and four dot products (38); per hit a cross
+# product, the norm, sqrt and three divisions with the sign (21).
+AA_BYTES_PER_PAIR = 12 * 8 + 3 * 8 + 2
+AA_EFT_OPS_PER_PAIR, AA_EFT_OPS_PER_HIT = 174, 254
+AA_NAIVE_OPS_PER_PAIR, AA_NAIVE_OPS_PER_HIT = 38, 21
+AA_METRIC = "arc x arc intersections/s (EFT vs naive FP64)"
+
+
+def cpu_baseline_arcarc(P, sample):
+    """The arc x arc oracle (exact integer orientations + 100-digit points) on a stratified
+    sample of the workload, all workers."""
+    import numpy as np
+    from oracle import batch as OB
+    idx = np.concatenate([np.flatnonzero(P.part == k)[: sample // 4] for k in range(4)])
+    S = P.take(idx)
+    workers = OB.default_workers()
+    t0 = time.perf_counter()
+    OB.arcarc_exact(S.a1, S.a2, S.b1, S.b2, workers=workers)
+    dt = time.perf_counter() - t0
+    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(S)} pairs, the first {sample // 4} of each of the 4 parts of the same "
+                      f"workload (exact integer orientations + 100-digit decimal points), "
+                      f"{dt:.1f} s wall", "cpu_model": cpu_model()}
+
+
+def cpu_replica_arcarc(P, sample, threads):
+    """Context only: the kernel's per-pair arithmetic compiled for the host, `threads` host
+    threads, over the first `sample` pairs."""
+    import ctypes
+    import threading
+    import numpy as np
+    path = os.path.join(ROOT, "paper_2510_09892_amd", "libsphint_hostcheck.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    lib.sphint_hostcheck_arcarc.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(dp),
+                                            ctypes.POINTER(dp), dp, dp, dp, ip, ip]
+    S = P.take(np.arange(min(sample, len(P))))
+    A, B = S.soa_a(), S.soa_b()
+    n = len(S)
+    out = {"threads": threads, "pairs": n, "unit": "intersections/s", "cpu_model": cpu_model(),
+           "kind": "host build of the kernel arithmetic (not the oracle)"}
+    for mode, name in ((1, "eft"), (0, "naive")):
+        res = [np.zeros(n) for _ in range(3)] + [np.zeros(n, np.int32) for _ in range(2)]
+        bounds = np.linspace(0, n, threads + 1).astype(np.int64)
+
+        def work(lo, hi):
+            pa = (dp * 6)(*[a[lo:hi].ctypes.data_as(dp) for a in A])
+            pb = (dp * 6)(*[b[lo:hi].ctypes.data_as(dp) for b in B])
+            lib.sphint_hostcheck_arcarc(mode, int(hi - lo), pa, pb,
+                                        *[r[lo:hi].ctypes.data_as(dp) for r in res[:3]],
+                                        *[r[lo:hi].ctypes.data_as(ip) for r in res[3:]])
+        ts = [threading.Thread(target=work, args=(bounds[k], bounds[k + 1])) for k in range(threads)]
+        t0 = time.perf_counter()
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        out[name] = n / (time.perf_counter() - t0)
+    return out
+
+
+def bench_arcarc(args, torch, np, inputs, sphint):
+    """1e7 arc x arc pairs (crossing-shaped, short, nearly parallel, shared-vertex quarters),
+    direct pairing; one sphint_arc_arc call (one kernel) per step."""
+    log(f"[bench] generating {args.n} arc x arc pairs")
+    P = inputs.arc_pairs(args.n)
+    n = len(P)
+    cpu = replica = None
+    if not args.no_cpu_baseline:
+        sample = max(args.cpu_sample, 1_000_000)
+        log(f"[bench] cpu baseline: arc x arc oracle on {sample} pairs")
+        replica = cpu_replica_arcarc(P, 4_000_000, min(os.cpu_count() or 1, 16))
+        cpu = cpu_baseline_arcarc(P, sample)
+        log(f"[bench] cpu baseline {cpu['value']:.0f} pairs/s on {cpu['cores']} workers")
+    a = [torch.from_numpy(v).cuda() for v in P.soa_a()]
+    b = [torch.from_numpy(v).cuda() for v in P.soa_b()]
+    torch.cuda.synchronize()
+    res = {}
+    for mode in args.modes.split(","):
+        out = sphint.ArcArcOutput(n)
+        call = lambda: sphint.arc_arc(tuple(a[:3]), tuple(a[3:]), tuple(b[:3]), tuple(b[3:]),
+                                      mode=mode, out=out)
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for e0, e1 in ev:  # events on the stream the kernel is launched on
+            e0.record()
+            call()
+            e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = [e0.elapsed_time(e1) for e0, e1 in ev]
+        hits = int(out.count.sum().item())
+        res[mode] = dict(wall_s=wall, kernel_ms=kms, hits=hits,
+                         exact=int(((out.flags & sphint.AA_EXACT) > 0).sum().item()))
+        log(f"[bench] arcarc {mode}: wall {wall / args.steps * 1e3:.4f} ms/step, kernel "
+            f"{statistics.mean(kms):.4f} ms, hits {hits}")
+
+    copy_calibration(torch, args.copy_calibration)
+
+    def roof(mode):
+        r = res[mode]
+        kms = statistics.mean(r["kernel_ms"])
+        byts = AA_BYTES_PER_PAIR * n
+        if mode == "eft":
+            ops = AA_EFT_OPS_PER_PAIR * n + AA_EFT_OPS_PER_HIT * r["hits"]
+        else:
+            ops = AA_NAIVE_OPS_PER_PAIR * n + AA_NAIVE_OPS_PER_HIT * r["hits"]
+        bw, rate = byts / (kms * 1e-3), ops / (kms * 1e-3)
+        hbm = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+               "frac": bw / HBM_PEAK}
+        alu = {"bound": "alu", "achieved": rate / 1e12, "peak": ALU_PEAK / 1e12,
+               "unit": "Tlane-op/s (binary64)", "frac": rate / ALU_PEAK}
+        out = dict(hbm if hbm["frac"] >= alu["frac"] else alu)
+        other = alu if out["bound"] == "hbm" else hbm
+        tr = measured_traffic(f"k_arc_arc_{mode}_arcarc1e7", source_digest())
+        out["traffic"] = tr["bytes"] if tr else None
+        if tr:
+            out["traffic_detail"] = tr
+        out["kernel"] = f"k_arc_arc<{1 if mode == 'eft' else 0}, false>"
+        out["kernel_ms"] = kms
+        out["kernel_ms_p10_p50_p90"] = pctl(r["kernel_ms"])
+        out["algorithmic_bytes"] = byts
+        out["algorithmic_ops"] = ops
+        out["other_bound"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+        return out
+
+    head = "eft" if "eft" in res else next(iter(res))
+    r = res[head]
+    value = n * args.steps / r["wall_s"]
+    line = {
+        "metric": AA_METRIC, "value": value, "unit": "intersections/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["wall_s"] / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "1e7 arc x arc pairs in four parts (crossing-shaped 0.05..1 rad; "
+                               "short 1e-9..1e-6 rad; nearly parallel, tilt 1e-9..1e-3; shared "
+                               "vertex), direct pairing, mode " + head,
+                   "pairs": n, "hits": r["hits"], "exact_fallback_pairs": r["exact"]},
+        "roofline": roof(head),
+    }
+    if "naive" in res and head != "naive":
+        rn = res["naive"]
+        nv = n * args.steps / rn["wall_s"]
+        line["naive"] = {"value": nv, "ms_per_step": rn["wall_s"] / args.steps * 1e3,
+                         "kernel_ms": statistics.mean(rn["kernel_ms"]), "hits": rn["hits"],
+                         "roofline": roof("naive")}
+        line["eft_over_naive"] = value / nv
+    if replica is not None:
+        line["cpu_replica"] = replica
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

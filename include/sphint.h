@@ -220,6 +220,54 @@ sphint_status sphint_candidates_fill(int64_t n_arcs, const int64_t *lat_offsets,
                                      int32_t *lat_idx, int64_t capacity, void *workspace,
                                      size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------ arc x arc intersections */
+
+/*
+ * Intersection of two minor great-circle arcs A = a1 -> a2 and B = b1 -> b2 (the further
+ * application the paper names for its accurate cross product, Sec. 1 and Sec. 9).  Their
+ * great circles meet at +-p, p = (a1 x a2) x (b1 x b2) / |(a1 x a2) x (b1 x b2)|; the
+ * result is the one of the two that lies on both closed arcs, if any.  With n_A = a1 x a2
+ * and n_B = b1 x b2, +p is on both arcs iff n_B.a1 >= 0 >= n_B.a2 and n_A.b2 >= 0 >= n_A.b1,
+ * -p iff all four inequalities are reversed (Binet-Cauchy on the containment tests);
+ * endpoints need not be unit length (the arcs are those of x/|x|).
+ *
+ * Modes:
+ *   SPHINT_NAIVE_FP64  every cross product, the four orientation signs, the norm and the
+ *                      divisions in plain binary64.
+ *   SPHINT_EFT_FP64    n_A and n_B by AccuDOP (Alg. 4) as compensated pairs; the four
+ *                      orientation signs exact (two filter stages, then exact expansion
+ *                      arithmetic); each component of n_A x n_B by CompDot (Alg. 2) over
+ *                      the pairs, |.|^2 by SumOfSquares (Alg. 5), one square root, three
+ *                      divisions.  Counts and flags are exact; the point is within a few
+ *                      units of 2^-53 of the exact one (the same input range as above).
+ *
+ * Pairs: pair k takes arc ia[k] of A (arc k when ia == NULL, then n_a must equal n_pairs)
+ * and arc ib[k] of B (likewise).  An index outside [0, n_a) / [0, n_b) yields a NONFINITE
+ * pair, never an access out of bounds.  a1, a2 have n_a entries per component, b1, b2 n_b
+ * (device).
+ * out         [n_pairs] per component (device): the point, (0, 0, 0) when there is none.
+ * out_count   [n_pairs] 0 or 1 (device, required).
+ * out_flags   [n_pairs] SPHINT_AA_* bits (device, may be NULL).
+ * No workspace; one kernel launch on `stream`.  SPHINT_E_INVAL (no launch) for negative
+ * sizes, missing pointers, a bad mode or a direct side whose size is not n_pairs;
+ * SPHINT_E_HIP if the launch fails.
+ */
+#define SPHINT_AA_HIT 1u       /* the arcs meet in one point */
+#define SPHINT_AA_DEGEN 4u     /* an arc has a zero normal (equal or antipodal endpoints) */
+#define SPHINT_AA_COPLANAR 8u  /* both arcs lie on one great circle: no isolated point */
+#define SPHINT_AA_NONFINITE 16u/* an input is inf or nan, or an index is out of range */
+#define SPHINT_AA_EXACT 32u    /* diagnostic (EFT): an orientation needed exact arithmetic */
+#define SPHINT_AA_INTERNAL 64u /* exact arithmetic exceeded its buffer (not for valid input) */
+
+typedef struct {
+  double *x, *y, *z;
+} sphint_pts_out;
+
+sphint_status sphint_arc_arc(int64_t n_pairs, sphint_pts_soa a1, sphint_pts_soa a2, int64_t n_a,
+                             sphint_pts_soa b1, sphint_pts_soa b2, int64_t n_b,
+                             const int32_t *ia, const int32_t *ib, sphint_pts_out out,
+                             uint8_t *out_count, uint8_t *out_flags, int mode, void *stream);
+
 const char *sphint_status_string(sphint_status s);
 /* "sphint <version> gfx950" */
 const char *sphint_version(void);

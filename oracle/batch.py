@@ -107,3 +107,21 @@ def accux_points(x1, y1, z1, x2, y2, z2, z0, roots_per_pair, workers=None):
     rows = _rows(x1, y1, z1, x2, y2, z2, z0)
     jobs = [r + (tuple(rt),) for r, rt in zip(rows, roots_per_pair)]
     return _map(_eft_chunk, jobs, workers)
+
+
+# ------------------------------------------------------------------ arc x arc
+
+def _arcarc_chunk(rows):
+    from . import arcarc
+    out = []
+    for (a1, a2, b1, b2) in rows:
+        count, flags, p = arcarc.intersect(a1, a2, b1, b2)
+        out.append((count, flags, p))
+    return out
+
+
+def arcarc_exact(a1, a2, b1, b2, workers=None):
+    """The arc x arc oracle over (n, 3) endpoint arrays: [(count, flags, point or None)]."""
+    rows = list(zip(*(map(tuple, np.asarray(v, dtype=np.float64).tolist())
+                      for v in (a1, a2, b1, b2))))
+    return _map(_arcarc_chunk, rows, workers)

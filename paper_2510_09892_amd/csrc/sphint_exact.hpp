@@ -140,6 +140,34 @@ __host__ __device__ inline int sum_sq3(double x, double y, double z, double* h) 
 
 }  // namespace xp
 
+// Exact sign of the determinant u . (v x w) (an orientation of three vectors from the
+// origin), in the caller's arena (xp::ARENA doubles).  Returns 2 if an expansion would
+// overflow the arena (never for inputs in the documented range).
+__host__ __device__ __noinline__ inline int exact_orient(double ux, double uy, double uz,
+                                                          double vx, double vy, double vz,
+                                                          double wx, double wy, double wz,
+                                                          double* arena) {
+  using namespace xp;
+  double* B0 = arena;
+  double* B1 = arena + CAP;
+  double* B2 = arena + 2 * CAP;
+  double* B3 = arena + 3 * CAP;
+  int l0 = diff_of_products(vy, wz, vz, wy, B0);  // (v x w)_x
+  int t = scale(l0, B0, ux, B1);
+  if (t < 0) return 2;
+  int l1 = diff_of_products(vz, wx, vx, wz, B0);  // (v x w)_y
+  int t2 = scale(l1, B0, uy, B2);
+  if (t2 < 0) return 2;
+  t = add_into(t, B1, t2, B2);
+  if (t < 0) return 2;
+  int l2 = diff_of_products(vx, wy, vy, wx, B0);  // (v x w)_z
+  t2 = scale(l2, B0, uz, B3);
+  if (t2 < 0) return 2;
+  t = add_into(t, B1, t2, B3);
+  if (t < 0) return 2;
+  return sign_of(compress(t, B1), B1);
+}
+
 // Which predicate exact_sign evaluates.
 enum : int {
   PRED_S2 = 0,  // sign(|n_xy|^2 - |n|^2 z0^2)              (Sec. 2 existence test)

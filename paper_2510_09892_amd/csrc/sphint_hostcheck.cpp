@@ -3,6 +3,7 @@
 // the same header the kernels use, so the CPU tests exercise the exact operation sequence
 // of the GPU evaluation; undecided predicates are resolved immediately instead of one lane
 // at a time.
+#include "sphint_arcarc.hpp"
 #include "sphint_cand.hpp"
 #include "sphint_pair.hpp"
 
@@ -50,4 +51,35 @@ extern "C" int sphint_hostcheck_candidates(int64_t n, const double* x1, const do
     sphint::arc_candidates(x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], lat_z, n_lat, pad, first[i],
                            count[i]);
   return 0;
+}
+
+// Arc x arc intersections, direct pairs: a = (ax1..az2)[i], b = (bx1..bz2)[i].
+extern "C" int sphint_hostcheck_arcarc(int mode, int64_t n, const double* const* a,
+                                       const double* const* b, double* px, double* py,
+                                       double* pz, int32_t* count, int32_t* flags) {
+  using namespace sphint;
+  static thread_local double arena[xp::ARENA];
+  for (int64_t i = 0; i < n; ++i) {
+    const double a1[3] = {a[0][i], a[1][i], a[2][i]}, a2[3] = {a[3][i], a[4][i], a[5][i]};
+    const double b1[3] = {b[0][i], b[1][i], b[2][i]}, b2[3] = {b[3][i], b[4][i], b[5][i]};
+    AAOut o;
+    if (mode == 1)
+      o = eval_aa_eft(true, a1, a2, b1, b2, arena, [](bool need, auto&& fn) {
+        if (need) fn();
+      });
+    else
+      o = eval_aa_naive(true, a1, a2, b1, b2);
+    px[i] = o.px;
+    py[i] = o.py;
+    pz[i] = o.pz;
+    count[i] = o.count;
+    flags[i] = (int32_t)o.flags;
+  }
+  return 0;
+}
+
+// Exact sign of u . (v x w).
+extern "C" int sphint_hostcheck_orient(const double* u, const double* v, const double* w) {
+  static thread_local double arena[sphint::xp::ARENA];
+  return sphint::exact_orient(u[0], u[1], u[2], v[0], v[1], v[2], w[0], w[1], w[2], arena);
 }

@@ -16,6 +16,10 @@ Workloads (sizes are defaults; tests pass smaller ones):
 * ``cubed_sphere``   all unique edges of an equiangular gnomonic cubed sphere with ne x ne
   cells per face, plus latitude lines, and CSR candidate lists from z-range overlap.
 * ``mesh_batch`` / ``request_stream``: many uneven meshes for batched and served runs.
+* ``arc_pairs``      arc x arc pairs in four equal parts: crossing-shaped arcs (B through a
+  point near A's midpoint, about half of them cross), short arcs (1e-9 to 1e-6 rad), nearly
+  parallel arcs (endpoints tilted by 1e-9 to 1e-3) and mesh-like shared vertices (b1 = a2
+  exactly).
 
 Endpoints are computed in binary64 and left as rounded (not re-normalised), so they are not
 exactly unit vectors, as the paper allows (Sec. 1.2 footnote).  The arc z-range used to
@@ -321,3 +325,72 @@ def request_stream(rate_hz: float = 2000.0, duration_s: float = 10.0, arcs_lo=1e
     lats = np.floor(np.exp(g.uniform(np.log(lat_lo), np.log(lat_hi + 1), n))).astype(int)
     lats = np.clip(lats, lat_lo, lat_hi)
     return t, [(int(a), int(L), 1000 + i) for i, (a, L) in enumerate(zip(arcs, lats))]
+
+
+# ----------------------------------------------------------------- arc x arc workloads
+
+class ArcPairs:
+    """Dense arc x arc pairs: A = a1 -> a2 and B = b1 -> b2, (n, 3) each; ``part`` labels."""
+
+    def __init__(self, a1, a2, b1, b2, part=None):
+        self.a1, self.a2, self.b1, self.b2 = (np.ascontiguousarray(v, dtype=np.float64)
+                                              for v in (a1, a2, b1, b2))
+        self.part = np.zeros(len(self.a1), np.int8) if part is None else np.asarray(part, np.int8)
+
+    def __len__(self):
+        return len(self.a1)
+
+    def soa_a(self):
+        return tuple(np.ascontiguousarray(v[:, c]) for v in (self.a1, self.a2) for c in range(3))
+
+    def soa_b(self):
+        return tuple(np.ascontiguousarray(v[:, c]) for v in (self.b1, self.b2) for c in range(3))
+
+    def take(self, idx):
+        return ArcPairs(self.a1[idx], self.a2[idx], self.b1[idx], self.b2[idx], self.part[idx])
+
+
+def _unit(v):
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def _through(g, c, half_lo, half_hi):
+    """An arc through c (unit, (n, 3)) along a uniform bearing, each half U[half_lo, half_hi]."""
+    n = len(c)
+    br = g.uniform(0.0, 2 * np.pi, n)
+    b1 = arc_from(c, g.uniform(half_lo, half_hi, n), br)
+    b2 = arc_from(c, g.uniform(half_lo, half_hi, n), br + np.pi)
+    return b1, b2
+
+
+def arc_pairs(n: int = 10_000_000, seed_tag: int = 5) -> ArcPairs:
+    g = rng(seed_tag)
+    sizes = [n // 4 + (1 if k < n % 4 else 0) for k in range(4)]
+    out = []
+    # (0) crossing-shaped: A of length U[0.05, 1], B through a point near A's midpoint
+    m = sizes[0]
+    a1 = random_unit(g, m)
+    a2 = arc_from(a1, g.uniform(0.05, 1.0, m), g.uniform(0.0, 2 * np.pi, m))
+    c = arc_from(_unit(a1 + a2), g.uniform(0.0, 0.5, m), g.uniform(0.0, 2 * np.pi, m))
+    out.append((a1, a2, *_through(g, _unit(c), 0.05, 0.5)))
+    # (1) short: A log-uniform in [1e-9, 1e-6] rad, B of half-length 1e-7 near its midpoint
+    m = sizes[1]
+    a1 = random_unit(g, m)
+    a2 = arc_from(a1, np.exp(g.uniform(np.log(1e-9), np.log(1e-6), m)),
+                  g.uniform(0.0, 2 * np.pi, m))
+    c = arc_from(_unit(a1 + a2), g.uniform(0.0, 1e-7, m), g.uniform(0.0, 2 * np.pi, m))
+    out.append((a1, a2, *_through(g, _unit(c), 1e-8, 1e-7)))
+    # (2) nearly parallel: B's endpoints are A's tilted by 1e-9 .. 1e-3
+    m = sizes[2]
+    a1 = random_unit(g, m)
+    a2 = arc_from(a1, np.full(m, 0.05), g.uniform(0.0, 2 * np.pi, m))
+    tilt = np.exp(g.uniform(np.log(1e-9), np.log(1e-3), (m, 1)))
+    out.append((a1, a2, a1 + tilt * random_unit(g, m), a2 + tilt * random_unit(g, m)))
+    # (3) mesh-like: B starts exactly at A's end (a shared vertex)
+    m = sizes[3]
+    a1 = random_unit(g, m)
+    a2 = arc_from(a1, g.uniform(1e-3, 0.05, m), g.uniform(0.0, 2 * np.pi, m))
+    b2 = arc_from(a2, g.uniform(1e-3, 0.05, m), g.uniform(0.0, 2 * np.pi, m))
+    out.append((a1, a2, a2.copy(), b2))
+    part = np.concatenate([np.full(sz, k, np.int8) for k, sz in enumerate(sizes)])
+    return ArcPairs(*(np.concatenate([o[i] for o in out]) for i in range(4)), part=part)

@@ -21,6 +21,7 @@ MODES = {"naive": NAIVE, "naive_fp64": NAIVE, "eft": EFT, "eft_fp64": EFT, NAIVE
 OK, E_INVAL, E_CAPACITY, E_HIP, E_NOMEM, E_DEVICE = range(6)
 F_EXISTS, F_TANGENT, F_DEGEN_N, F_HORIZ, F_NONFINITE = 1, 2, 4, 8, 16
 ROOT_PLUS, ROOT_MINUS = 0, 1
+AA_HIT, AA_DEGEN, AA_COPLANAR, AA_NONFINITE, AA_EXACT, AA_INTERNAL = 1, 4, 8, 16, 32, 64
 
 EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_set_profile_events",
@@ -29,6 +30,7 @@ EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_plan_destroy",
            "sphint_candidates_workspace_size", "sphint_candidates_count",
            "sphint_candidates_fill",
+           "sphint_arc_arc",
            "sphint_status_string",
            "sphint_version")
 
@@ -96,6 +98,9 @@ def load():
     lib.sphint_candidates_count.restype = ctypes.c_int
     lib.sphint_candidates_fill.argtypes = [i64, vp, vp, i64, vp, sz, vp]
     lib.sphint_candidates_fill.restype = ctypes.c_int
+    lib.sphint_arc_arc.argtypes = [i64, PtsSoA, PtsSoA, i64, PtsSoA, PtsSoA, i64, vp, vp,
+                                   PtsSoA, vp, vp, ctypes.c_int, vp]
+    lib.sphint_arc_arc.restype = ctypes.c_int
     lib.sphint_plan_destroy.argtypes = [vp]
     lib.sphint_plan_destroy.restype = None
     lib.sphint_status_string.argtypes = [ctypes.c_int]
@@ -234,6 +239,47 @@ def candidates(p1, p2, lat_z, pad=0.0, stream=None):
     _check(lib.sphint_candidates_fill(n_arcs, _ptr(off), _ptr(idx), n, _ptr(ws), wsb, st),
            "sphint_candidates_fill")
     return off, idx[:n]
+
+
+class ArcArcOutput:
+    """Dense per-pair results of sphint_arc_arc: point (x, y, z), count (0/1), flags."""
+
+    def __init__(self, n_pairs, flags=True, device="cuda"):
+        import torch
+        self.n = n_pairs
+        self.x, self.y, self.z = (torch.empty(n_pairs, dtype=torch.float64, device=device)
+                                  for _ in range(3))
+        self.count = torch.empty(n_pairs, dtype=torch.uint8, device=device)
+        self.flags = torch.empty(n_pairs, dtype=torch.uint8, device=device) if flags else None
+
+
+def arc_arc(a1, a2, b1, b2, ia=None, ib=None, mode="eft", out=None, stream=None):
+    """Enqueue sphint_arc_arc: pair k is arc ia[k] of A = a1 -> a2 with arc ib[k] of
+    B = b1 -> b2 (arc k when an index tensor is None; int32 index tensors).  Returns the
+    ArcArcOutput; nothing is synchronised."""
+    import torch
+    lib = load()
+    sa1, n_a = _soa(a1)
+    sa2, n2 = _soa(a2)
+    sb1, n_b = _soa(b1)
+    sb2, n3 = _soa(b2)
+    if n2 != n_a or n3 != n_b:
+        raise SphintError("arc endpoint arrays differ in length")
+    for t in (ia, ib):
+        if t is not None and (t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous()):
+            raise SphintError("pair indices must be contiguous int32 CUDA tensors")
+    if ia is not None and ib is not None and len(ia) != len(ib):
+        raise SphintError("ia and ib differ in length")
+    n = len(ia) if ia is not None else (len(ib) if ib is not None else n_a)
+    if out is None:
+        out = ArcArcOutput(n, device=a1[0].device)
+    if out.n != n:
+        raise SphintError("output buffers sized for a different number of pairs")
+    st = lib.sphint_arc_arc(n, sa1, sa2, n_a, sb1, sb2, n_b, _ptr(ia), _ptr(ib),
+                            PtsSoA(out.x.data_ptr(), out.y.data_ptr(), out.z.data_ptr()),
+                            _ptr(out.count), _ptr(out.flags), MODES[mode], _stream(stream))
+    _check(st, "sphint_arc_arc")
+    return out
 
 
 def arc_constlat_raw(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, hits, count,

@@ -1,0 +1,209 @@
+"""GPU: arc x arc intersections (sphint_arc_arc) through the C ABI, against the oracle.
+
+* Small and ragged batches: counts and flags equal the exact oracle, EFT points equal its
+  binary64 replica bit for bit and lie within 4 * 2^-53 of the exact points, naive results
+  equal the plain binary64 replica (tests/test_hostcheck_arcarc.py's comparison).
+* Indexed pairs equal the direct evaluation of the gathered arcs; out-of-range indices give
+  NONFINITE pairs; one-sided indexing; a batch larger than one grid pass.
+* The full 1e7-pair workload in the benchmark's launch configuration: a stratified sample
+  against the oracle, every pair against the CPU build of the same code, and the
+  shared-vertex quarter (whose point is the shared vertex) as a property over every pair.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2510_09892_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from test_hostcheck_arcarc import (  # noqa: E402
+    LIBPATH, as_tuples, oracle_compare, run as host_run, soa, special_pairs)
+
+U = 2.0 ** -53
+
+
+def note(msg):
+    print(f"[gpu-arcarc] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hc():
+    import ctypes
+    lib = ctypes.CDLL(LIBPATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib.sphint_hostcheck_arcarc.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.POINTER(dp),
+                                            ctypes.POINTER(dp), dp, dp, dp, ip, ip]
+    return lib
+
+
+def dev(torch, arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def gpu(torch, A, B, mode, ia=None, ib=None):
+    """A, B: six host arrays each; returns (count, flags, x, y, z) host arrays."""
+    from paper_2510_09892_amd import sphint
+    a, b = dev(torch, A), dev(torch, B)
+    dia = None if ia is None else torch.from_numpy(np.ascontiguousarray(ia, np.int32)).cuda()
+    dib = None if ib is None else torch.from_numpy(np.ascontiguousarray(ib, np.int32)).cuda()
+    out = sphint.arc_arc(tuple(a[0:3]), tuple(a[3:6]), tuple(b[0:3]), tuple(b[3:6]), dia, dib,
+                         mode=mode)
+    torch.cuda.synchronize()
+    return (out.count.cpu().numpy().astype(np.int32), out.flags.cpu().numpy().astype(np.int32),
+            out.x.cpu().numpy(), out.y.cpu().numpy(), out.z.cpu().numpy())
+
+
+def both(torch, pairs):
+    a, b = soa(pairs)
+    return gpu(torch, a, b, "eft"), gpu(torch, a, b, "naive")
+
+
+def test_small_batch_against_oracle(torch_cuda):
+    import itertools
+    pairs = special_pairs() + as_tuples(inputs.arc_pairs(4000, seed_tag=60))
+    verts = [v for v in itertools.product((-1.0, 0.0, 1.0, 2.0), repeat=3) if any(v)]
+    g = np.random.Generator(np.random.PCG64(94))
+    pairs += [tuple(verts[int(i)] for i in g.integers(0, len(verts), 4)) for _ in range(1003)]
+    note(f"small batch: {len(pairs)} pairs")
+    eft, naive = both(torch_cuda, pairs)
+    n_hits, n_exact = oracle_compare(pairs, eft, naive)
+    assert n_hits > 1500 and n_exact > 300
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 255, 257, 1023])
+def test_ragged_sizes(torch_cuda, n):
+    pairs = as_tuples(inputs.arc_pairs(n, seed_tag=61 + n))
+    note(f"ragged n={n}")
+    eft, naive = both(torch_cuda, pairs)
+    oracle_compare(pairs, eft, naive)
+
+
+def test_indexed_pairs_equal_direct_evaluation(torch_cuda):
+    P = inputs.arc_pairs(3000, seed_tag=70)
+    Q = inputs.arc_pairs(2000, seed_tag=71)
+    A = P.soa_a()
+    B = Q.soa_b()
+    g = np.random.Generator(np.random.PCG64(95))
+    m = 20011
+    ia = g.integers(0, 3000, m).astype(np.int32)
+    ib = g.integers(0, 2000, m).astype(np.int32)
+    bad = g.choice(m, 40, replace=False)
+    ia[bad[:10]] = -1
+    ia[bad[10:20]] = 3000
+    ib[bad[20:30]] = -7
+    ib[bad[30:]] = 2000
+    note(f"indexed: {m} pairs over {len(P)} x {len(Q)} arcs")
+    okm = np.ones(m, bool)
+    okm[bad] = False
+    for mode in ("eft", "naive"):
+        got = gpu(torch_cuda, A, B, mode, ia, ib)
+        ga = [a[np.clip(ia, 0, 2999)] for a in A]
+        gb = [b[np.clip(ib, 0, 1999)] for b in B]
+        ref = gpu(torch_cuda, ga, gb, mode)
+        for g_, r_ in zip(got, ref):
+            assert np.array_equal(g_[okm], r_[okm], equal_nan=True)
+        assert np.all(got[0][bad] == 0) and np.all(got[1][bad] == 16)
+        assert np.all(got[2][bad] == 0) and np.all(got[3][bad] == 0) and np.all(got[4][bad] == 0)
+    # a sample of the indexed pairs against the oracle
+    sel = np.nonzero(okm)[0][:400]
+    pairs = [tuple(tuple(float(x) for x in (A[3 * s][ia[k]], A[3 * s + 1][ia[k]], A[3 * s + 2][ia[k]]))
+                   for s in (0, 1)) +
+             tuple(tuple(float(x) for x in (B[3 * s][ib[k]], B[3 * s + 1][ib[k]], B[3 * s + 2][ib[k]]))
+                   for s in (0, 1)) for k in sel]
+    eft = [a[sel] for a in gpu(torch_cuda, A, B, "eft", ia, ib)]
+    naive = [a[sel] for a in gpu(torch_cuda, A, B, "naive", ia, ib)]
+    oracle_compare(pairs, eft, naive)
+
+
+def test_one_sided_index(torch_cuda):
+    P = inputs.arc_pairs(900, seed_tag=72)
+    Q = inputs.arc_pairs(50, seed_tag=73)
+    ib = np.random.Generator(np.random.PCG64(96)).integers(0, 50, 900).astype(np.int32)
+    note("one-sided index")
+    got = gpu(torch_cuda, P.soa_a(), Q.soa_b(), "eft", None, ib)
+    ref = gpu(torch_cuda, P.soa_a(), [b[ib] for b in Q.soa_b()], "eft")
+    for g_, r_ in zip(got, ref):
+        assert np.array_equal(g_, r_, equal_nan=True)
+
+
+def test_more_pairs_than_one_grid_pass(torch_cuda):
+    """2^24 + 4099 indexed pairs over 64 x 64 arcs: more lanes than the grid holds (the
+    kernel loops); every pair equals its entry of the 64 x 64 table."""
+    P = inputs.arc_pairs(64, seed_tag=74)
+    Q = inputs.arc_pairs(64, seed_tag=75)
+    A, B = P.soa_a(), Q.soa_b()
+    ii, jj = np.meshgrid(np.arange(64, dtype=np.int32), np.arange(64, dtype=np.int32),
+                         indexing="ij")
+    table = gpu(torch_cuda, [a[ii.ravel()] for a in A], [b[jj.ravel()] for b in B], "eft")
+    m = (1 << 24) + 4099
+    g = np.random.Generator(np.random.PCG64(97))
+    ia = g.integers(0, 64, m).astype(np.int32)
+    ib = g.integers(0, 64, m).astype(np.int32)
+    note(f"grid-stride: {m} pairs")
+    got = gpu(torch_cuda, A, B, "eft", ia, ib)
+    key = ia.astype(np.int64) * 64 + ib
+    for g_, t_ in zip(got, table):
+        assert np.array_equal(g_, t_[key], equal_nan=True)
+
+
+def test_empty_call(torch_cuda):
+    from paper_2510_09892_amd import sphint
+    z = torch_cuda.zeros(0, dtype=torch_cuda.float64, device="cuda")
+    out = sphint.arc_arc((z, z, z), (z, z, z), (z, z, z), (z, z, z))
+    torch_cuda.cuda.synchronize()
+    assert out.n == 0
+
+
+@pytest.fixture(scope="module")
+def full(torch_cuda):
+    note("full size: generating 1e7 arc pairs")
+    P = inputs.arc_pairs(10_000_000)
+    A, B = P.soa_a(), P.soa_b()
+    note("full size: GPU eft and naive")
+    return P, A, B, gpu(torch_cuda, A, B, "eft"), gpu(torch_cuda, A, B, "naive")
+
+
+def test_full_size_sample_against_oracle(full):
+    P, A, B, eft, naive = full
+    g = np.random.Generator(np.random.PCG64(98))
+    sel = np.concatenate([g.choice(np.nonzero(P.part == k)[0], 500, replace=False)
+                          for k in range(4)])
+    note(f"full size: {len(sel)} sampled pairs against the oracle")
+    pairs = as_tuples(P.take(sel))
+    n_hits, _ = oracle_compare(pairs, [a[sel] for a in eft], [a[sel] for a in naive])
+    assert n_hits > 1000
+
+
+def test_full_size_equals_host_build(full, hc):
+    P, A, B, eft, naive = full
+    note("full size: every pair against the CPU build")
+    for mode, res in ((1, eft), (0, naive)):
+        ref = host_run(hc, mode, A, B)
+        for g_, r_ in zip(res, ref):
+            assert np.array_equal(g_, r_, equal_nan=True)
+
+
+def test_full_size_shared_vertex_property(full):
+    """B starts at A's end: every such pair meets at that vertex, normalised."""
+    P, A, B, eft, naive = full
+    sel = P.part == 3
+    c, f, x, y, z = (a[sel] for a in eft)
+    assert np.all(c == 1) and np.all(f & 1)
+    v = P.a2[sel]
+    v = v / np.linalg.norm(v, axis=1, keepdims=True)
+    err = np.max(np.abs(np.stack([x, y, z], axis=1) - v))
+    assert err <= 6 * U, err / U  # 4 u for the point, 2 u for numpy's normalisation

@@ -80,3 +80,27 @@ def test_batch_rejects_bad_arguments():
     assert lib.sphint_batch_plan_create(arr, 1, 1, ctypes.byref(h)) == sphint.E_INVAL
     assert lib.sphint_batch_launch(None, None) == sphint.E_INVAL
     assert lib.sphint_set_profile_events(ctypes.c_void_p(1), None) == sphint.E_INVAL
+
+
+def _aa(**kw):
+    lib = sphint.load()
+    P = sphint.PtsSoA
+    d = dict(n=4, a1=P(1, 2, 3), a2=P(4, 5, 6), n_a=4, b1=P(7, 8, 9), b2=P(10, 11, 12), n_b=4,
+             ia=None, ib=None, out=P(13, 14, 15), count=16, flags=None, mode=1, stream=None)
+    d.update(kw)
+    return lib.sphint_arc_arc(d["n"], d["a1"], d["a2"], d["n_a"], d["b1"], d["b2"], d["n_b"],
+                              d["ia"], d["ib"], d["out"], d["count"], d["flags"], d["mode"],
+                              d["stream"])
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=-1), dict(n_a=-1, ia=100), dict(n_a=3), dict(n_b=5), dict(mode=2), dict(count=None),
+    dict(out=sphint.PtsSoA(13, None, 15)), dict(a2=sphint.PtsSoA(4, 5, None)),
+    dict(b1=sphint.PtsSoA(None, 8, 9), ib=100, n_b=1),
+])
+def test_arc_arc_invalid_arguments_rejected_before_launch(bad):
+    assert _aa(**bad) == sphint.E_INVAL
+
+
+def test_arc_arc_empty_call_is_a_no_op():
+    assert _aa(n=0, n_a=0, n_b=0, count=None, out=sphint.PtsSoA(None, None, None)) == sphint.OK
