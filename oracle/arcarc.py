@@ -22,9 +22,11 @@ Points: p in 100-digit decimal from the exact integer vector (n_A x n_B).  Along
 binary64 replicas of the library's two evaluations, step by step:
 * naive: every cross product, the norm and the division in plain binary64;
 * EFT: n_A and n_B by AccuDOP (Alg. 4, read as in the latitude path) with the TwoSum
-  renormalisation, each component of n_A x n_B as CompDot (Alg. 2) over the eight
-  TwoProducts of the renormalised pairs, |X|^2 by SumOfSquares (Alg. 5), one binary64
-  square root and three divisions.
+  renormalisation; each component X_c = nA_i nB_j - nA_j nB_i of n_A x n_B by AccuDOP on
+  the leading parts, with the four first-order products of the trailing parts (one
+  multiplication and three FMAs) added to its error term before the final sum (the
+  second-order products are below u^2 of the result and are dropped); |X|^2 by
+  SumOfSquares (Alg. 5), one binary64 square root and three divisions.
 """
 
 from __future__ import annotations
@@ -135,11 +137,15 @@ def eft_point(a1, a2, b1, b2, sign):
     nA = _normal_pairs(a1, a2)
     nB = _normal_pairs(b1, b2)
 
-    def comp(i, j):  # (nA_i nB_j - nA_j nB_i) over the hi/lo parts, Alg. 2
+    def comp(i, j):  # nA_i nB_j - nA_j nB_i over the (leading, trailing) pairs
         (ai, ei), (aj, ej) = nA[i], nA[j]
         (bi, fi), (bj, fj) = nB[i], nB[j]
-        return E.comp_dot([ai, ai, ei, ei, -aj, -aj, -ej, -ej],
-                          [bj, fj, bj, fj, bi, fi, bi, fi])
+        dop, err = E.accu_dop(ai, bj, aj, bi)
+        t = ai * fj
+        t = E.fma(ei, bj, t)
+        t = E.fma(-aj, fi, t)
+        t = E.fma(-ej, bi, t)
+        return dop + (err + t)
 
     X = (comp(1, 2), comp(2, 0), comp(0, 1))
     S, s = E.sum_of_squares(X)

@@ -55,21 +55,6 @@ constexpr int WG_PER_CU_SINGLE = 4;  // resident workgroups per CU of the persis
 
 thread_local hipEvent_t prof_start = nullptr, prof_stop = nullptr;
 
-// Compute units of the current device (queried once per device).
-int device_cus() {
-  static int cached[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!cached[dev]) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    cached[dev] = cus;
-  }
-  return cached[dev];
-}
-
 // Workgroups of k_intersect_w<MODE, wppt_single<MODE>(), CSR> one CU holds at once
 // (queried once).
 template <int MODE, bool CSR>

@@ -1,9 +1,7 @@
 // C-ABI entry point for arc x arc intersections (include/sphint.h).
 //
-// One lane per pair, a block-uniform grid-stride loop (the exact fallback is scheduled
-// over the wavefront's lanes with a ballot, so every lane of a wavefront takes the same
-// trips).  Pairs either pair arc k of A with arc k of B (direct) or gather both arcs by
-// int32 index (indexed); every output is written densely, one entry per pair, with
+// One lane per pair.  Pairs either pair arc k of A with arc k of B (direct) or gather both
+// arcs by int32 index (indexed); every output is written densely, one entry per pair, with
 // per-lane consecutive (coalesced) stores.  The work per pair is a few hundred binary64
 // operations and 122 bytes of traffic in the direct form, so both modes sit near the
 // HBM roofline at full occupancy; nothing here needs a workspace or a device-wide
@@ -22,7 +20,7 @@ using namespace sphint;
 namespace {
 
 constexpr int AA_BLOCK = 256;
-constexpr int64_t AA_MAX_BLOCKS = 1 << 16;
+constexpr int64_t AA_MAX_BLOCKS = 1 << 16;  // beyond this the grid loops
 
 struct AAArgs {
   const double *ax1, *ay1, *az1, *ax2, *ay2, *az2;
@@ -33,8 +31,12 @@ struct AAArgs {
   uint8_t *ocount, *oflags;
 };
 
-// Loads endpoint k of one side; an index outside [0, n) reads nothing and gives NaN (the pair
-// is then reported NONFINITE).
+struct AAIn {
+  double a1[3], a2[3], b1[3], b2[3];
+};
+
+// Loads one side's arc i; an index outside [0, n) reads nothing and gives NaN (the pair is
+// then reported NONFINITE).
 __device__ __forceinline__ void load_arc(const double* x1, const double* y1, const double* z1,
                                          const double* x2, const double* y2, const double* z2,
                                          int64_t i, bool ok, double* p, double* q) {
@@ -47,30 +49,39 @@ __device__ __forceinline__ void load_arc(const double* x1, const double* y1, con
   q[2] = ok ? z2[i] : nan;
 }
 
+// Pair k's four endpoints (nothing is read when k >= n).
+template <bool IDX>
+__device__ __forceinline__ void load_pair(const AAArgs& g, int64_t k, AAIn& in) {
+  const bool valid = k < g.n;
+  int64_t i = k, j = k;
+  if (IDX) {
+    if (valid && g.ia) i = g.ia[k];
+    if (valid && g.ib) j = g.ib[k];
+  }
+  const bool oka = valid && i >= 0 && i < g.n_a;
+  const bool okb = valid && j >= 0 && j < g.n_b;
+  load_arc(g.ax1, g.ay1, g.az1, g.ax2, g.ay2, g.az2, i, oka, in.a1, in.a2);
+  load_arc(g.bx1, g.by1, g.bz1, g.bx2, g.by2, g.bz2, j, okb, in.b1, in.b2);
+}
+
+// One lane per pair over a block-uniform grid-stride loop (the exact fallback's ballot sees
+// whole wavefronts).  Loads are not software-pipelined: with the wavefronts this register
+// budget allows resident, a prefetch of the next chunk measured slower.
 template <int MODE, bool IDX>
 __global__ __launch_bounds__(AA_BLOCK) void k_arc_arc(AAArgs g) {
   const int64_t stride = (int64_t)gridDim.x * AA_BLOCK;
   for (int64_t k0 = (int64_t)blockIdx.x * AA_BLOCK; k0 < g.n; k0 += stride) {
     const int64_t k = k0 + threadIdx.x;
     const bool valid = k < g.n;
-    int64_t i = k, j = k;
-    if (IDX) {
-      if (valid && g.ia) i = g.ia[k];
-      if (valid && g.ib) j = g.ib[k];
-    }
-    const bool oka = valid && i >= 0 && i < g.n_a;
-    const bool okb = valid && j >= 0 && j < g.n_b;
-    double a1[3], a2[3], b1[3], b2[3];
-    load_arc(g.ax1, g.ay1, g.az1, g.ax2, g.ay2, g.az2, i, oka, a1, a2);
-    load_arc(g.bx1, g.by1, g.bz1, g.bx2, g.by2, g.bz2, j, okb, b1, b2);
+    AAIn in;
+    load_pair<IDX>(g, k, in);
     AAOut o;
     if constexpr (MODE == SPHINT_EFT_FP64) {
       __shared__ double arena[AA_BLOCK / 64][xp::ARENA];
-      o = eval_aa_eft(valid, a1, a2, b1, b2, arena[threadIdx.x >> 6], [](bool need, auto&& fn) {
-        resolve_serial(need, fn);
-      });
+      o = eval_aa_eft(valid, in.a1, in.a2, in.b1, in.b2, arena[threadIdx.x >> 6],
+                      [](bool need, auto&& fn) { resolve_serial(need, fn); });
     } else {
-      o = eval_aa_naive(valid, a1, a2, b1, b2);
+      o = eval_aa_naive(valid, in.a1, in.a2, in.b1, in.b2);
     }
     if (valid) {
       g.ox[k] = o.px;

@@ -11,8 +11,8 @@
 //
 // EFT mode: n_A, n_B by AccuDOP (Alg. 4) renormalised by TwoSum; the signs certified by two
 // filter stages and decided exactly (exact_orient) when both fail; each component of
-// n_A x n_B as CompDot (Alg. 2) over the eight TwoProducts of the renormalised pairs; |X|^2 by
-// SumOfSquares (Alg. 5); one binary64 square root and three divisions.  Naive mode: plain
+// n_A x n_B by AccuDOP on the leading parts plus the trailing parts' first-order products;
+// |X|^2 by SumOfSquares (Alg. 5); one binary64 square root and three divisions.  Naive mode: plain
 // binary64 throughout (signs included).
 #pragma once
 #pragma clang fp contract(off)
@@ -179,23 +179,22 @@ __host__ __device__ __forceinline__ AAOut eval_aa_eft(bool valid, const double* 
   o.flags = fl | (need ? AA_EXACT : 0u) | (ok ? 0u : AA_INTERNAL);
   if (sg == 0) return o;
   o.count = 1;
-  // X = n_A x n_B, each component CompDot over the hi/lo products (i, j) = (1,2), (2,0), (0,1)
+  // X = n_A x n_B: component c = nA_i nB_j - nA_j nB_i, (i, j) = (1,2), (2,0), (0,1), by
+  // AccuDOP on the leading parts with the trailing parts' first-order products (one
+  // multiplication, three FMAs) added to its error term; the second-order products are
+  // below u^2 of the result.
   double X[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int i = (c + 1) % 3, j = (c + 2) % 3;
-    const double xs[8] = {A.n[i], A.n[i], A.e[i], A.e[i], -A.n[j], -A.n[j], -A.e[j], -A.e[j]};
-    const double ys[8] = {B.n[j], B.e[j], B.n[j], B.e[j], B.n[i], B.e[i], B.n[i], B.e[i]};
-    dd p = two_prod(xs[0], ys[0]);
-    double ph = p.hi, s = p.lo;
-#pragma unroll
-    for (int k = 1; k < 8; ++k) {
-      const dd h = two_prod(xs[k], ys[k]);
-      const dd q = two_sum(ph, h.hi);
-      ph = q.hi;
-      s = s + (q.lo + h.lo);
-    }
-    X[c] = ph + s;
+    const dd p1 = two_prod(A.n[i], B.n[j]), p2 = two_prod(A.n[j], B.n[i]);
+    const dd d = two_sum(p1.hi, -p2.hi);
+    const double err = d.lo + (p1.lo - p2.lo);
+    double t = A.n[i] * B.e[j];
+    t = __builtin_fma(A.e[i], B.n[j], t);
+    t = __builtin_fma(-A.n[j], B.e[i], t);
+    t = __builtin_fma(-A.e[j], B.n[i], t);
+    X[c] = d.hi + (err + t);
   }
   dd S = two_prod(X[0], X[0]);  // SumOfSquares (Alg. 5)
   S = sum_non_neg(S, two_prod(X[1], X[1]));

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "sphint.h"
@@ -21,6 +22,21 @@ inline int64_t wave_tiles_for(int64_t nnz, int wppt) {
 }
 
 inline bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+// Compute units of the current device (queried once per device).
+inline int device_cus() {
+  static std::atomic<int> cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int c = cached[dev].load(std::memory_order_relaxed);
+  if (!c) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        c <= 0)
+      c = 256;
+    cached[dev].store(c, std::memory_order_relaxed);
+  }
+  return c;
+}
 
 // Workspace of one call over nnz pairs: header, one status word per tile of the finest
 // schedule (64 pairs), then the CSR pair-to-arc table (4 bytes per pair).
