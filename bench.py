@@ -529,11 +529,12 @@ def bench_batch(args, torch, np, inputs, sphint):
 # Arc x arc: per pair, four endpoints read (12 binary64) and the point, count and flags
 # written.  Operations as counted for the latitude path: EFT normals (two AccuDOP cross
 # products, TwoSum-renormalised: 114) and the first filter stage of four orientations (60)
-# per pair; per hit three eight-term CompDots, SumOfSquares, sqrt, three divisions and the
-# sign (254).  Naive: two cross products and four dot products (38); per hit a cross
+# per pair; per hit three compensated cross-product components (AccuDOP on the leading parts
+# plus four first-order products: 18 each), SumOfSquares, sqrt, three divisions and the sign
+# (85).  Naive: two cross products and four dot products (38); per hit a cross
 # product, the norm, sqrt and three divisions with the sign (21).
 AA_BYTES_PER_PAIR = 12 * 8 + 3 * 8 + 2
-AA_EFT_OPS_PER_PAIR, AA_EFT_OPS_PER_HIT = 174, 254
+AA_EFT_OPS_PER_PAIR, AA_EFT_OPS_PER_HIT = 174, 85
 AA_NAIVE_OPS_PER_PAIR, AA_NAIVE_OPS_PER_HIT = 38, 21
 AA_METRIC = "arc x arc intersections/s (EFT vs naive FP64)"
 
