@@ -323,10 +323,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--workload", default="ill1e7",
-                    choices=["ill1e7", "cubed1024", "batch64", "arcarc1e7"],
+                    choices=["ill1e7", "cubed1024", "batch64", "arcarc1e7", "adaptive"],
                     help="ill1e7: the headline (1e7 ill-conditioned dense pairs); cubed1024: "
                          "regridding-shaped CSR; batch64: 64 uneven meshes in one launch; "
-                         "arcarc1e7: 1e7 arc x arc pairs")
+                         "arcarc1e7: 1e7 arc x arc pairs; adaptive: filtered direct/EFT "
+                         "evaluation on 1e7 uniform and 1e7 ill-conditioned pairs")
     ap.add_argument("--modes", default="eft,naive")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -352,6 +353,8 @@ def main():
         return bench_batch(args, torch, np, inputs, sphint)
     if args.workload == "arcarc1e7":
         return bench_arcarc(args, torch, np, inputs, sphint)
+    if args.workload == "adaptive":
+        return bench_adaptive(args, torch, np, inputs, sphint)
     if args.workload == "cubed1024":
         log("[bench] generating the ne=1024 cubed sphere x 1800 latitudes")
         mesh = inputs.cubed_sphere(1024)
@@ -688,6 +691,73 @@ def bench_arcarc(args, torch, np, inputs, sphint):
         line["cpu_replica"] = replica
     if cpu is not None:
         line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
+
+
+ADAPTIVE_TOLS = (0.0, 4.0, 16.0, 64.0, 1024.0)
+
+
+def bench_adaptive(args, torch, np, inputs, sphint):
+    """Adaptive evaluation (direct binary64 with a running error bound, EFT for the rest) on
+    1e7 uniform and 1e7 ill-conditioned dense pairs, at several tolerances, beside the EFT and
+    naive calls of the main path on the same inputs."""
+    sets = {}
+    for name in ("uniform", "ill"):
+        log(f"[bench] generating 1e7 {name} pairs")
+        P = (inputs.uniform_arcs(args.n, seed_tag=0) if name == "uniform"
+             else inputs.ill_conditioned(args.n, seed_tag=1))
+        sets[name] = [torch.from_numpy(a).cuda() for a in P.soa()]
+    torch.cuda.synchronize()
+
+    def timed(call):
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record()
+            call()
+            e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall / args.steps * 1e3, statistics.mean(e0.elapsed_time(e1) for e0, e1 in ev)
+
+    table = {}
+    for name, d in sets.items():
+        n = len(d[6])
+        row = {}
+        for mode in ("eft", "naive"):
+            out = sphint.Output(n)
+            ms, dev_ms = timed(lambda: sphint.arc_constlat(tuple(d[:3]), tuple(d[3:6]), d[6],
+                                                           mode=mode, out=out))
+            row[mode] = {"ms_per_call": ms, "device_ms": dev_ms, "pairs_per_s": n / (ms * 1e-3)}
+        out = sphint.AdaptiveOutput(n)
+        for tol in ADAPTIVE_TOLS:
+            ms, dev_ms = timed(lambda: sphint.arc_constlat_adaptive(tuple(d[:3]), tuple(d[3:6]),
+                                                                    d[6], tol, out=out))
+            rec = int(out.recomputed.item())
+            row[f"tol{tol:g}"] = {"ms_per_call": ms, "device_ms": dev_ms,
+                                  "pairs_per_s": n / (ms * 1e-3), "recomputed": rec,
+                                  "recomputed_frac": rec / n}
+            log(f"[bench] adaptive {name} tol={tol:g}: {ms:.4f} ms/call, recomputed {rec / n:.4f}")
+        log(f"[bench] {name}: eft {row['eft']['ms_per_call']:.4f} ms, naive "
+            f"{row['naive']['ms_per_call']:.4f} ms")
+        table[name] = row
+    head = table["uniform"]["tol64"]
+    line = {
+        "metric": "adaptive arc-latitude intersections/s (points within tol*2^-53, exact decisions)",
+        "value": head["pairs_per_s"], "unit": "intersections/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_call"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "1e7 uniform pairs (d ~ U[1e-3, 0.2] rad), dense, adaptive "
+                               "tol = 64 (value); the table adds tol 0/4/16/1024, the 1e7 "
+                               "ill-conditioned workload, and the EFT and naive calls",
+                   "pairs": args.n},
+        "adaptive": table,
+    }
     print(json.dumps(line), flush=True)
 
 

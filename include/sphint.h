@@ -220,6 +220,44 @@ sphint_status sphint_candidates_fill(int64_t n_arcs, const int64_t *lat_offsets,
                                      int32_t *lat_idx, int64_t capacity, void *workspace,
                                      size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------ adaptive evaluation */
+
+/*
+ * Filtered switching between the direct binary64 evaluation and the EFT evaluation, which
+ * the paper names as future work (Sec. 9), for dense pairs (pair i = arc i with latitude
+ * z0[i]).  Pass 1 evaluates Eq. 2.2 in binary64, operation for operation as
+ * SPHINT_NAIVE_FP64 does, and bounds its own rounding error as it goes; a pair is accepted
+ * when the bound certifies every decision (the slope signs, the sign of s^2 and the height
+ * comparisons against the normalised endpoints: the exact decisions of SPHINT_EFT_FP64) and
+ * each point lies within tol * 2^-53 (max-norm) of the exact intersection.  Every other pair
+ * (tangencies among them) goes to a queue that pass 2 evaluates with SPHINT_EFT_FP64's
+ * arithmetic; those pairs carry SPHINT_F_RECOMPUTED.  So counts, roots and flags equal the
+ * EFT mode's exactly, and every point is within max(tol, 4) * 2^-53 of the exact one.
+ * tol = 0 sends every pair with an intersection to pass 2.
+ *
+ * out         dense per-pair output (device): slots 2i and 2i+1 hold pair i's hits in
+ *             along-arc order, unused slots hold 0; out.root and out.flags may be NULL.
+ * out_recomputed  one int64 (device, may be NULL): the number of pairs pass 2 evaluated.
+ * workspace   device memory of at least sphint_adaptive_workspace_size(n) bytes, 256-byte
+ *             aligned, used only by this call while it runs.
+ * n < 2^32.  SPHINT_E_INVAL (no launch) for a negative or too large n, tol < 0 or NaN,
+ * missing pointers or a short or misaligned workspace; SPHINT_E_HIP if a launch fails.
+ */
+#define SPHINT_F_RECOMPUTED 128u /* adaptive: evaluated by the EFT pass */
+
+typedef struct {
+  double *x, *y;  /* [2 n] */
+  uint8_t *root;  /* [2 n] SPHINT_ROOT_*, may be NULL */
+  uint8_t *count; /* [n] 0..2 */
+  uint8_t *flags; /* [n] SPHINT_F_*, may be NULL */
+} sphint_dense_out;
+
+size_t sphint_adaptive_workspace_size(int64_t n);
+sphint_status sphint_arc_constlat_adaptive(int64_t n, sphint_pts_soa p1, sphint_pts_soa p2,
+                                           const double *z0, double tol, sphint_dense_out out,
+                                           int64_t *out_recomputed, void *workspace,
+                                           size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------ arc x arc intersections */
 
 /*

@@ -3,6 +3,7 @@
 // the same header the kernels use, so the CPU tests exercise the exact operation sequence
 // of the GPU evaluation; undecided predicates are resolved immediately instead of one lane
 // at a time.
+#include "sphint_adaptive.hpp"
 #include "sphint_arcarc.hpp"
 #include "sphint_cand.hpp"
 #include "sphint_pair.hpp"
@@ -82,4 +83,35 @@ extern "C" int sphint_hostcheck_arcarc(int mode, int64_t n, const double* const*
 extern "C" int sphint_hostcheck_orient(const double* u, const double* v, const double* w) {
   static thread_local double arena[sphint::xp::ARENA];
   return sphint::exact_orient(u[0], u[1], u[2], v[0], v[1], v[2], w[0], w[1], w[2], arena);
+}
+
+// The adaptive evaluation: pass 1, and the EFT evaluation for the pairs it does not accept
+// (cert[i] = 1 when pass 1 accepted pair i).
+extern "C" int sphint_hostcheck_adaptive(int64_t n, const double* x1, const double* y1,
+                                         const double* z1, const double* x2, const double* y2,
+                                         const double* z2, const double* z0, double tol,
+                                         int32_t* count, int32_t* flags, int32_t* r0,
+                                         int32_t* r1, double* px0, double* py0, double* px1,
+                                         double* py1, int32_t* cert) {
+  using namespace sphint;
+  static thread_local double arena[xp::ARENA];
+  for (int64_t i = 0; i < n; ++i) {
+    PairOut o;
+    const bool c = adaptive_pass1(x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], z0[i], tol, o);
+    if (!c)
+      o = eval_eft(true, x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], z0[i], arena,
+                   [](bool need, auto&& fn) {
+                     if (need) fn();
+                   });
+    count[i] = o.count;
+    flags[i] = (int32_t)(o.flags & 127u);
+    r0[i] = o.count ? o.r0 : 0;
+    r1[i] = o.count == 2 ? o.r1 : 0;
+    px0[i] = o.count ? o.px0 : 0.0;
+    py0[i] = o.count ? o.py0 : 0.0;
+    px1[i] = o.count == 2 ? o.px1 : 0.0;
+    py1[i] = o.count == 2 ? o.py1 : 0.0;
+    cert[i] = c;
+  }
+  return 0;
 }

@@ -21,6 +21,7 @@ MODES = {"naive": NAIVE, "naive_fp64": NAIVE, "eft": EFT, "eft_fp64": EFT, NAIVE
 OK, E_INVAL, E_CAPACITY, E_HIP, E_NOMEM, E_DEVICE = range(6)
 F_EXISTS, F_TANGENT, F_DEGEN_N, F_HORIZ, F_NONFINITE = 1, 2, 4, 8, 16
 ROOT_PLUS, ROOT_MINUS = 0, 1
+F_RECOMPUTED = 128
 AA_HIT, AA_DEGEN, AA_COPLANAR, AA_NONFINITE, AA_EXACT, AA_INTERNAL = 1, 4, 8, 16, 32, 64
 
 EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
@@ -31,6 +32,7 @@ EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_candidates_workspace_size", "sphint_candidates_count",
            "sphint_candidates_fill",
            "sphint_arc_arc",
+           "sphint_adaptive_workspace_size", "sphint_arc_constlat_adaptive",
            "sphint_status_string",
            "sphint_version")
 
@@ -42,6 +44,11 @@ class PtsSoA(ctypes.Structure):
 class Hits(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("pair", ctypes.c_void_p),
                 ("root", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+class DenseOut(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("root", ctypes.c_void_p),
+                ("count", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
 
 
 class MeshDesc(ctypes.Structure):
@@ -101,6 +108,11 @@ def load():
     lib.sphint_arc_arc.argtypes = [i64, PtsSoA, PtsSoA, i64, PtsSoA, PtsSoA, i64, vp, vp,
                                    PtsSoA, vp, vp, ctypes.c_int, vp]
     lib.sphint_arc_arc.restype = ctypes.c_int
+    lib.sphint_adaptive_workspace_size.argtypes = [i64]
+    lib.sphint_adaptive_workspace_size.restype = sz
+    lib.sphint_arc_constlat_adaptive.argtypes = [i64, PtsSoA, PtsSoA, vp, ctypes.c_double,
+                                                 DenseOut, vp, vp, sz, vp]
+    lib.sphint_arc_constlat_adaptive.restype = ctypes.c_int
     lib.sphint_plan_destroy.argtypes = [vp]
     lib.sphint_plan_destroy.restype = None
     lib.sphint_status_string.argtypes = [ctypes.c_int]
@@ -279,6 +291,50 @@ def arc_arc(a1, a2, b1, b2, ia=None, ib=None, mode="eft", out=None, stream=None)
                             PtsSoA(out.x.data_ptr(), out.y.data_ptr(), out.z.data_ptr()),
                             _ptr(out.count), _ptr(out.flags), MODES[mode], _stream(stream))
     _check(st, "sphint_arc_arc")
+    return out
+
+
+class AdaptiveOutput:
+    """Dense per-pair results of sphint_arc_constlat_adaptive (two slots per pair)."""
+
+    def __init__(self, n, device="cuda"):
+        import torch
+        self.n = n
+        self.x = torch.empty(2 * n, dtype=torch.float64, device=device)
+        self.y = torch.empty(2 * n, dtype=torch.float64, device=device)
+        self.root = torch.empty(2 * n, dtype=torch.uint8, device=device)
+        self.count = torch.empty(n, dtype=torch.uint8, device=device)
+        self.flags = torch.empty(n, dtype=torch.uint8, device=device)
+        self.recomputed = torch.zeros(1, dtype=torch.int64, device=device)
+        ws = int(load().sphint_adaptive_workspace_size(n))
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=device)
+        self.ws_bytes = ws
+
+    def struct(self):
+        return DenseOut(self.x.data_ptr(), self.y.data_ptr(), self.root.data_ptr(),
+                        self.count.data_ptr(), self.flags.data_ptr())
+
+
+def arc_constlat_adaptive(p1, p2, z0, tol, out=None, stream=None):
+    """Enqueue sphint_arc_constlat_adaptive (dense pairs: arc i with latitude z0[i]); points
+    within max(tol, 4) * 2^-53 of the exact ones.  Returns the AdaptiveOutput; nothing is
+    synchronised."""
+    import torch
+    lib = load()
+    s1, n = _soa(p1)
+    s2, n2 = _soa(p2)
+    if n2 != n or len(z0) != n:
+        raise SphintError("p1, p2 and z0 differ in length")
+    if z0.dtype != torch.float64 or not z0.is_cuda:
+        raise SphintError("z0 must be a float64 CUDA tensor")
+    if out is None:
+        out = AdaptiveOutput(n, device=z0.device)
+    if out.n != n:
+        raise SphintError("output buffers sized for a different number of pairs")
+    st = lib.sphint_arc_constlat_adaptive(n, s1, s2, _ptr(z0), float(tol), out.struct(),
+                                          _ptr(out.recomputed), _ptr(out.workspace), out.ws_bytes,
+                                          _stream(stream))
+    _check(st, "sphint_arc_constlat_adaptive")
     return out
 
 

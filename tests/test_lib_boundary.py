@@ -104,3 +104,24 @@ def test_arc_arc_invalid_arguments_rejected_before_launch(bad):
 
 def test_arc_arc_empty_call_is_a_no_op():
     assert _aa(n=0, n_a=0, n_b=0, count=None, out=sphint.PtsSoA(None, None, None)) == sphint.OK
+
+
+def test_adaptive_workspace_and_invalid_arguments():
+    lib = sphint.load()
+    assert lib.sphint_adaptive_workspace_size(0) == 256
+    assert lib.sphint_adaptive_workspace_size(64) == 256 + 256
+    assert lib.sphint_adaptive_workspace_size(65) == 256 + 512
+    P = sphint.PtsSoA
+    out = sphint.DenseOut(1, 2, None, 3, None)
+
+    def call(**kw):
+        d = dict(n=4, p1=P(1, 2, 3), p2=P(4, 5, 6), z0=7, tol=16.0, out=out, rec=None, ws=256,
+                 wsb=1 << 20)
+        d.update(kw)
+        return lib.sphint_arc_constlat_adaptive(d["n"], d["p1"], d["p2"], d["z0"], d["tol"],
+                                                d["out"], d["rec"], d["ws"], d["wsb"], None)
+    for bad in (dict(n=-1), dict(n=1 << 32), dict(tol=-1.0), dict(tol=float("nan")),
+                dict(ws=None), dict(ws=260), dict(wsb=300), dict(z0=None),
+                dict(p2=P(4, None, 6)), dict(out=sphint.DenseOut(1, None, None, 3, None)),
+                dict(out=sphint.DenseOut(1, 2, None, None, None))):
+        assert call(**bad) == sphint.E_INVAL, bad
