@@ -323,11 +323,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--workload", default="ill1e7",
-                    choices=["ill1e7", "cubed1024", "batch64", "arcarc1e7", "adaptive"],
+                    choices=["ill1e7", "cubed1024", "batch64", "arcarc1e7", "adaptive",
+                             "ablation"],
                     help="ill1e7: the headline (1e7 ill-conditioned dense pairs); cubed1024: "
                          "regridding-shaped CSR; batch64: 64 uneven meshes in one launch; "
                          "arcarc1e7: 1e7 arc x arc pairs; adaptive: filtered direct/EFT "
-                         "evaluation on 1e7 uniform and 1e7 ill-conditioned pairs")
+                         "evaluation on 1e7 uniform and 1e7 ill-conditioned pairs; ablation: "
+                         "the alternative point formulas")
     ap.add_argument("--modes", default="eft,naive")
     ap.add_argument("--cpu-sample", type=int, default=300_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -355,6 +357,8 @@ def main():
         return bench_arcarc(args, torch, np, inputs, sphint)
     if args.workload == "adaptive":
         return bench_adaptive(args, torch, np, inputs, sphint)
+    if args.workload == "ablation":
+        return bench_ablation(args, torch, np, inputs, sphint)
     if args.workload == "cubed1024":
         log("[bench] generating the ne=1024 cubed sphere x 1800 latitudes")
         mesh = inputs.cubed_sphere(1024)
@@ -757,6 +761,48 @@ def bench_adaptive(args, torch, np, inputs, sphint):
                                "ill-conditioned workload, and the EFT and naive calls",
                    "pairs": args.n},
         "adaptive": table,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_ablation(args, torch, np, inputs, sphint):
+    """Throughput of each point formula (sphint_circle_points: both circle points per pair,
+    no containment) on the 1e7 ill-conditioned pairs.  Their accuracy is measured against the
+    exact points by the GPU tests (tests/test_gpu_ablation.py prints the table)."""
+    log(f"[bench] generating {args.n} ill-conditioned arcs")
+    P = inputs.ill_conditioned(args.n, seed_tag=1)
+    d = [torch.from_numpy(a).cuda() for a in P.soa()]
+    n = len(P)
+    rows = {}
+    for name in sphint.FORMULAS:
+        call = lambda: sphint.circle_points(tuple(d[:3]), tuple(d[3:6]), d[6], name)
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record()
+            call()
+            e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        kms = statistics.mean(e0.elapsed_time(e1) for e0, e1 in ev)
+        # 56 B read, 32 B of points and 1 B written per pair
+        rows[name] = {"ms_per_call": wall * 1e3, "device_ms": kms, "pairs_per_s": n / wall,
+                      "hbm_frac": 89 * n / (kms * 1e-3) / HBM_PEAK}
+        log(f"[bench] formula {name}: {kms:.4f} ms device, {n / wall:.3g} pairs/s")
+    head = rows["accux"]
+    line = {
+        "metric": "circle-intersection point pairs/s by formula (accuracy in the GPU tests)",
+        "value": head["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_call"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "1e7 ill-conditioned pairs, both circle points per pair, "
+                               "formula accux (value); the table adds eq22, eq21, eq71, kahan",
+                   "pairs": n},
+        "formulas": rows,
     }
     print(json.dumps(line), flush=True)
 

@@ -258,6 +258,34 @@ sphint_status sphint_arc_constlat_adaptive(int64_t n, sphint_pts_soa p1, sphint_
                                            int64_t *out_recomputed, void *workspace,
                                            size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------ alternative point formulas */
+
+/*
+ * For accuracy comparisons (Sec. 7's comparison of formulas, Sec. S2 on Kahan's
+ * determinant): both points where the great circle of x1 -> x2 meets the latitude circle
+ * z = z0, by one formula in binary64, with no containment test.  Formulas:
+ *   SPHINT_FORMULA_EQ22   Eq. (2.2) on n = x1 x x2, directly (the naive mode's arithmetic);
+ *   SPHINT_FORMULA_EQ21   Eq. (2.1) on the unit normal n / |n|;
+ *   SPHINT_FORMULA_EQ71   Eq. (7.1): Eq. (2.1) with the denominator 1 - n^z^2;
+ *   SPHINT_FORMULA_KAHAN  Eq. (2.2) with n by Kahan's DiffOfProd (Alg. 3);
+ *   SPHINT_FORMULA_ACCUX  AccuX (Alg. 8), the EFT mode's arithmetic.
+ * out_x, out_y  [2 n] (device): slot 2i the upper-sign point (SPHINT_ROOT_PLUS), slot 2i+1
+ *               the lower one; 0 where the formula gives none.
+ * out_ok        [n] (device): 1 where the formula's s^2 is non-negative and its
+ *               denominator positive, else 0.
+ * Dense pairs (arc i with z0[i]), one launch.  SPHINT_E_INVAL (no launch) for n < 0, an
+ * unknown formula or missing pointers; SPHINT_E_HIP if the launch fails.
+ */
+#define SPHINT_FORMULA_EQ22 0
+#define SPHINT_FORMULA_EQ21 1
+#define SPHINT_FORMULA_EQ71 2
+#define SPHINT_FORMULA_KAHAN 3
+#define SPHINT_FORMULA_ACCUX 4
+
+sphint_status sphint_circle_points(int64_t n, sphint_pts_soa p1, sphint_pts_soa p2,
+                                   const double *z0, int formula, double *out_x, double *out_y,
+                                   uint8_t *out_ok, void *stream);
+
 /* ------------------------------------------------------------ arc x arc intersections */
 
 /*

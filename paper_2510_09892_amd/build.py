@@ -23,7 +23,7 @@ HOSTCHECK = os.path.join(PKG, "libsphint_hostcheck.so")
 ARCH = os.environ.get("SPHINT_ARCH", "gfx950")
 
 DEVICE_SOURCES = ["sphint.hip", "sphint_batch.hip", "sphint_cand.hip", "sphint_arcarc.hip",
-                  "sphint_adaptive.hip"]
+                  "sphint_adaptive.hip", "sphint_ablation.hip"]
 COMMON = ["-O3", "-fPIC", "-shared", "-std=c++17", "-ffp-contract=off",
           f"-I{INCLUDE}", f"-I{CSRC}"]
 

@@ -3,6 +3,7 @@
 // the same header the kernels use, so the CPU tests exercise the exact operation sequence
 // of the GPU evaluation; undecided predicates are resolved immediately instead of one lane
 // at a time.
+#include "sphint_ablation.hpp"
 #include "sphint_adaptive.hpp"
 #include "sphint_arcarc.hpp"
 #include "sphint_cand.hpp"
@@ -112,6 +113,29 @@ extern "C" int sphint_hostcheck_adaptive(int64_t n, const double* x1, const doub
     px1[i] = o.count == 2 ? o.px1 : 0.0;
     py1[i] = o.count == 2 ? o.py1 : 0.0;
     cert[i] = c;
+  }
+  return 0;
+}
+
+// Both circle points of each pair by one alternative formula (SPHINT_FORMULA_EQ22..KAHAN).
+extern "C" int sphint_hostcheck_circle(int formula, int64_t n, const double* x1, const double* y1,
+                                       const double* z1, const double* x2, const double* y2,
+                                       const double* z2, const double* z0, double* ox, double* oy,
+                                       int32_t* ok) {
+  using namespace sphint;
+  for (int64_t i = 0; i < n; ++i) {
+    CirclePoints c;
+    switch (formula) {
+      case ABL_EQ22: c = circle_points<ABL_EQ22>(x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], z0[i]); break;
+      case ABL_EQ21: c = circle_points<ABL_EQ21>(x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], z0[i]); break;
+      case ABL_EQ71: c = circle_points<ABL_EQ71>(x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], z0[i]); break;
+      default: c = circle_points<ABL_KAHAN>(x1[i], y1[i], z1[i], x2[i], y2[i], z2[i], z0[i]); break;
+    }
+    ox[2 * i] = c.xp;
+    oy[2 * i] = c.yp;
+    ox[2 * i + 1] = c.xm;
+    oy[2 * i + 1] = c.ym;
+    ok[i] = c.ok;
   }
   return 0;
 }

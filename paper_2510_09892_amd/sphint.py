@@ -33,6 +33,7 @@ EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_candidates_fill",
            "sphint_arc_arc",
            "sphint_adaptive_workspace_size", "sphint_arc_constlat_adaptive",
+           "sphint_circle_points",
            "sphint_status_string",
            "sphint_version")
 
@@ -113,6 +114,8 @@ def load():
     lib.sphint_arc_constlat_adaptive.argtypes = [i64, PtsSoA, PtsSoA, vp, ctypes.c_double,
                                                  DenseOut, vp, vp, sz, vp]
     lib.sphint_arc_constlat_adaptive.restype = ctypes.c_int
+    lib.sphint_circle_points.argtypes = [i64, PtsSoA, PtsSoA, vp, ctypes.c_int, vp, vp, vp, vp]
+    lib.sphint_circle_points.restype = ctypes.c_int
     lib.sphint_plan_destroy.argtypes = [vp]
     lib.sphint_plan_destroy.restype = None
     lib.sphint_status_string.argtypes = [ctypes.c_int]
@@ -336,6 +339,30 @@ def arc_constlat_adaptive(p1, p2, z0, tol, out=None, stream=None):
                                           _stream(stream))
     _check(st, "sphint_arc_constlat_adaptive")
     return out
+
+
+FORMULAS = {"eq22": 0, "eq21": 1, "eq71": 2, "kahan": 3, "accux": 4}
+
+
+def circle_points(p1, p2, z0, formula, stream=None):
+    """Enqueue sphint_circle_points: both great-circle x latitude-circle points of every
+    dense pair by one formula (name or SPHINT_FORMULA_* value).  Returns (x [2n], y [2n],
+    ok [n]) device tensors; nothing is synchronised."""
+    import torch
+    lib = load()
+    s1, n = _soa(p1)
+    s2, n2 = _soa(p2)
+    if n2 != n or len(z0) != n:
+        raise SphintError("p1, p2 and z0 differ in length")
+    if z0.dtype != torch.float64 or not z0.is_cuda:
+        raise SphintError("z0 must be a float64 CUDA tensor")
+    f = FORMULAS.get(formula, formula)
+    x = torch.empty(2 * n, dtype=torch.float64, device=z0.device)
+    y = torch.empty(2 * n, dtype=torch.float64, device=z0.device)
+    ok = torch.empty(n, dtype=torch.uint8, device=z0.device)
+    _check(lib.sphint_circle_points(n, s1, s2, _ptr(z0), int(f), _ptr(x), _ptr(y), _ptr(ok),
+                                    _stream(stream)), "sphint_circle_points")
+    return x, y, ok
 
 
 def arc_constlat_raw(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, hits, count,

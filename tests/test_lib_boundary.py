@@ -108,9 +108,12 @@ def test_arc_arc_empty_call_is_a_no_op():
 
 def test_adaptive_workspace_and_invalid_arguments():
     lib = sphint.load()
-    assert lib.sphint_adaptive_workspace_size(0) == 256
-    assert lib.sphint_adaptive_workspace_size(64) == 256 + 256
-    assert lib.sphint_adaptive_workspace_size(65) == 256 + 512
+    # 64 queue counters 128 bytes apart, then 64 queue regions of ceil(chunks / 64) * 256
+    # entries (4 bytes), chunks = ceil(n / 256)
+    assert lib.sphint_adaptive_workspace_size(0) == 8192
+    assert lib.sphint_adaptive_workspace_size(64) == 8192 + 4 * 64 * 256
+    assert lib.sphint_adaptive_workspace_size(256 * 65) == 8192 + 4 * 64 * 512
+    assert lib.sphint_adaptive_workspace_size(10_000_000) == 8192 + 4 * 64 * 611 * 256
     P = sphint.PtsSoA
     out = sphint.DenseOut(1, 2, None, 3, None)
 
@@ -121,7 +124,23 @@ def test_adaptive_workspace_and_invalid_arguments():
         return lib.sphint_arc_constlat_adaptive(d["n"], d["p1"], d["p2"], d["z0"], d["tol"],
                                                 d["out"], d["rec"], d["ws"], d["wsb"], None)
     for bad in (dict(n=-1), dict(n=1 << 32), dict(tol=-1.0), dict(tol=float("nan")),
-                dict(ws=None), dict(ws=260), dict(wsb=300), dict(z0=None),
+                dict(ws=None), dict(ws=260), dict(wsb=8192), dict(z0=None),
                 dict(p2=P(4, None, 6)), dict(out=sphint.DenseOut(1, None, None, 3, None)),
                 dict(out=sphint.DenseOut(1, 2, None, None, None))):
         assert call(**bad) == sphint.E_INVAL, bad
+
+
+def test_circle_points_invalid_arguments():
+    lib = sphint.load()
+    P = sphint.PtsSoA
+    ok = dict(n=4, p1=P(1, 2, 3), p2=P(4, 5, 6), z0=7, f=0, x=8, y=9, o=10)
+
+    def call(**kw):
+        d = dict(ok)
+        d.update(kw)
+        return lib.sphint_circle_points(d["n"], d["p1"], d["p2"], d["z0"], d["f"], d["x"], d["y"],
+                                        d["o"], None)
+    for bad in (dict(n=-1), dict(f=-1), dict(f=5), dict(z0=None), dict(x=None), dict(o=None),
+                dict(p1=P(1, None, 3))):
+        assert call(**bad) == sphint.E_INVAL, bad
+    assert call(n=0, z0=None, x=None, y=None, o=None) == sphint.OK
