@@ -252,6 +252,19 @@ def cpu_baseline(P, inputs, sample):
             "single_core_value": len(S1) / d1, "cpu_model": cpu_model()}
 
 
+def cpu_baseline_dense(P, sample, what):
+    """The oracle on the first `sample` pairs of a dense workload, all workers."""
+    from oracle import batch as OB
+    S = P.take(slice(0, sample))
+    workers = OB.default_workers()
+    t0 = time.perf_counter()
+    OB.exact(*S.soa(), workers=workers)
+    dt = time.perf_counter() - t0
+    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(S)} pairs, {what} (exact integer predicates + 100-digit decimal "
+                      f"points), {dt:.1f} s wall", "cpu_model": cpu_model()}
+
+
 def cpu_replica(P, sample, threads):
     """Context only: the library's own per-pair arithmetic compiled for the host (the CPU
     check library, one evaluation per pair, exact fallbacks inline), on `threads` host
@@ -728,7 +741,13 @@ def bench_adaptive(args, torch, np, inputs, sphint):
         wall = time.perf_counter() - t0
         return wall / args.steps * 1e3, statistics.mean(e0.elapsed_time(e1) for e0, e1 in ev)
 
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_sample} uniform pairs")
+        cpu = cpu_baseline_dense(inputs.uniform_arcs(args.n, seed_tag=0), args.cpu_sample,
+                                 "the first pairs of the 1e7 uniform workload")
     table = {}
+    pass1 = {}
     for name, d in sets.items():
         n = len(d[6])
         row = {}
@@ -742,13 +761,34 @@ def bench_adaptive(args, torch, np, inputs, sphint):
             ms, dev_ms = timed(lambda: sphint.arc_constlat_adaptive(tuple(d[:3]), tuple(d[3:6]),
                                                                     d[6], tol, out=out))
             rec = int(out.recomputed.item())
+            timer = sphint.KernelTimer(args.steps)  # pass 1 alone (library events)
+            for k in range(args.steps):
+                timer.arm(k)
+                sphint.arc_constlat_adaptive(tuple(d[:3]), tuple(d[3:6]), d[6], tol, out=out)
+            torch.cuda.synchronize()
+            timer.disarm()
+            p1 = timer.durations_ms()
+            timer.close()
             row[f"tol{tol:g}"] = {"ms_per_call": ms, "device_ms": dev_ms,
+                                  "pass1_ms": statistics.mean(p1),
                                   "pairs_per_s": n / (ms * 1e-3), "recomputed": rec,
                                   "recomputed_frac": rec / n}
+            pass1[(name, tol)] = (p1, rec)
             log(f"[bench] adaptive {name} tol={tol:g}: {ms:.4f} ms/call, recomputed {rec / n:.4f}")
         log(f"[bench] {name}: eft {row['eft']['ms_per_call']:.4f} ms, naive "
             f"{row['naive']['ms_per_call']:.4f} ms")
         table[name] = row
+    # roofline of pass 1 (the kernel every pair goes through) at tol 64 on the uniform pairs:
+    # 56 B read per pair, 36 B of dense output per accepted pair, a 4-byte queue entry per
+    # queued pair
+    p1, rec = pass1[("uniform", 64.0)]
+    n = args.n
+    byts = 56 * n + 36 * (n - rec) + 4 * rec
+    kms = statistics.mean(p1)
+    bw = byts / (kms * 1e-3)
+    roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": bw / HBM_PEAK, "traffic": None, "kernel": "k_adapt_pass1", "kernel_ms": kms,
+            "kernel_ms_p10_p50_p90": pctl(p1), "algorithmic_bytes": byts}
     head = table["uniform"]["tol64"]
     line = {
         "metric": "adaptive arc-latitude intersections/s (points within tol*2^-53, exact decisions)",
@@ -760,8 +800,11 @@ def bench_adaptive(args, torch, np, inputs, sphint):
                                "tol = 64 (value); the table adds tol 0/4/16/1024, the 1e7 "
                                "ill-conditioned workload, and the EFT and naive calls",
                    "pairs": args.n},
+        "roofline": roof,
         "adaptive": table,
     }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 
@@ -771,9 +814,14 @@ def bench_ablation(args, torch, np, inputs, sphint):
     exact points by the GPU tests (tests/test_gpu_ablation.py prints the table)."""
     log(f"[bench] generating {args.n} ill-conditioned arcs")
     P = inputs.ill_conditioned(args.n, seed_tag=1)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle on {args.cpu_sample} pairs")
+        cpu = cpu_baseline(P, inputs, args.cpu_sample)
     d = [torch.from_numpy(a).cuda() for a in P.soa()]
     n = len(P)
     rows = {}
+    kmss = {}
     for name in sphint.FORMULAS:
         call = lambda: sphint.circle_points(tuple(d[:3]), tuple(d[3:6]), d[6], name)
         for _ in range(args.warmup):
@@ -788,12 +836,19 @@ def bench_ablation(args, torch, np, inputs, sphint):
             e1.record()
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
-        kms = statistics.mean(e0.elapsed_time(e1) for e0, e1 in ev)
+        kmss[name] = [e0.elapsed_time(e1) for e0, e1 in ev]
+        kms = statistics.mean(kmss[name])
         # 56 B read, 32 B of points and 1 B written per pair
         rows[name] = {"ms_per_call": wall * 1e3, "device_ms": kms, "pairs_per_s": n / wall,
                       "hbm_frac": 89 * n / (kms * 1e-3) / HBM_PEAK}
         log(f"[bench] formula {name}: {kms:.4f} ms device, {n / wall:.3g} pairs/s")
     head = rows["accux"]
+    byts = 89 * n
+    bw = byts / (head["device_ms"] * 1e-3)
+    roof = {"bound": "hbm", "achieved": bw / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": bw / HBM_PEAK, "traffic": None, "kernel": "k_circle<4>",
+            "kernel_ms": head["device_ms"], "kernel_ms_p10_p50_p90": pctl(kmss["accux"]),
+            "algorithmic_bytes": byts}
     line = {
         "metric": "circle-intersection point pairs/s by formula (accuracy in the GPU tests)",
         "value": head["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
@@ -802,8 +857,11 @@ def bench_ablation(args, torch, np, inputs, sphint):
         "config": {"workload": "1e7 ill-conditioned pairs, both circle points per pair, "
                                "formula accux (value); the table adds eq22, eq21, eq71, kahan",
                    "pairs": n},
+        "roofline": roof,
         "formulas": rows,
     }
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

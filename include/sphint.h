@@ -134,8 +134,9 @@ sphint_status sphint_check(const void *workspace, int64_t host_total, int64_t ca
 /*
  * Instrumentation.  While set (non-NULL), every sphint_arc_constlat call made from this host
  * thread records `start` (a hipEvent_t) on its stream immediately before its main kernel and
- * `stop` immediately after it, so the caller can time that kernel alone; NULL, NULL stops
- * it.  The events are owned by the caller.
+ * `stop` immediately after it, so the caller can time that kernel alone, and every
+ * sphint_arc_constlat_adaptive call does the same around its pass 1; NULL, NULL stops it.
+ * The events are owned by the caller.
  */
 sphint_status sphint_set_profile_events(void *start, void *stop);
 

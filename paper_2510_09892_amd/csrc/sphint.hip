@@ -53,7 +53,6 @@ constexpr int wppt_single() {
 }
 constexpr int WG_PER_CU_SINGLE = 4;  // resident workgroups per CU of the persistent grid
 
-thread_local hipEvent_t prof_start = nullptr, prof_stop = nullptr;
 
 // Workgroups of k_intersect_w<MODE, wppt_single<MODE>(), CSR> one CU holds at once
 // (queried once).
@@ -122,20 +121,21 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
 
   KArgs k = make_args(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out, out_count,
                       out_flags, out_total, ws, status, ntiles, parc);
-  if (prof_start && hipEventRecord(prof_start, st) != hipSuccess) return SPHINT_E_HIP;
+  if (profile_events().start && hipEventRecord(profile_events().start, st) != hipSuccess)
+    return SPHINT_E_HIP;
   const bool csr = lat_offsets != nullptr;
   hipError_t e;
   if (mode == SPHINT_EFT_FP64) e = csr ? launch_main<1, true>(k, st) : launch_main<1, false>(k, st);
   else e = csr ? launch_main<0, true>(k, st) : launch_main<0, false>(k, st);
-  if (e == hipSuccess && prof_stop) e = hipEventRecord(prof_stop, st);
+  if (e == hipSuccess && profile_events().stop) e = hipEventRecord(profile_events().stop, st);
   if (e == hipSuccess) e = chain.end();
   return e == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
 }
 
 extern "C" sphint_status sphint_set_profile_events(void* start, void* stop) {
   if ((start == nullptr) != (stop == nullptr)) return SPHINT_E_INVAL;
-  prof_start = (hipEvent_t)start;
-  prof_stop = (hipEvent_t)stop;
+  profile_events().start = (hipEvent_t)start;
+  profile_events().stop = (hipEvent_t)stop;
   return SPHINT_OK;
 }
 

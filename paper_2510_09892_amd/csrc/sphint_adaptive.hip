@@ -29,7 +29,6 @@ constexpr int64_t AD_MAX_BLOCKS = 1 << 16;
 constexpr int NQ = 64;             // queues
 constexpr size_t COUNTER_STRIDE = 16;  // counters 128 bytes apart (in 8-byte words)
 constexpr size_t AD_HEADER = NQ * COUNTER_STRIDE * 8;
-constexpr unsigned F_RECOMPUTED = 128u;
 
 // Entries per queue: queue q takes the chunks c with c % NQ == q.
 int64_t queue_region(int64_t n) {
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(AD_BLOCK) void k_adapt_pass2(AdArgs g) {
     }
     const PairOut o = eval_eft(ok, x1, y1, z1, x2, y2, z2, z0, arena[threadIdx.x >> 6],
                                [](bool need, auto&& fn) { resolve_serial(need, fn); });
-    if (ok) write_pair(g, k, o, F_RECOMPUTED);
+    if (ok) write_pair(g, k, o, SPHINT_F_RECOMPUTED);
   }
 }
 
@@ -169,8 +168,11 @@ extern "C" sphint_status sphint_arc_constlat_adaptive(int64_t n, sphint_pts_soa 
     }
     return SPHINT_OK;
   }
+  const ProfileEvents& pe = profile_events();
+  if (pe.start && hipEventRecord(pe.start, st) != hipSuccess) return SPHINT_E_HIP;
   hipLaunchKernelGGL(k_adapt_pass1, dim3((unsigned)ad_blocks(n)), dim3(AD_BLOCK), 0, st, g);
   if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
+  if (pe.stop && hipEventRecord(pe.stop, st) != hipSuccess) return SPHINT_E_HIP;
   // pass 2: a grid the device holds at once, walking the queue
   int64_t b2 = (int64_t)4 * device_cus();
   const int64_t bn = ad_blocks(n);

@@ -23,6 +23,18 @@ inline int64_t wave_tiles_for(int64_t nnz, int wppt) {
 
 inline bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
 
+// Events a caller asked to have recorded around the timed kernel of each call on this thread
+// (sphint_set_profile_events): the main kernel of sphint_arc_constlat, pass 1 of
+// sphint_arc_constlat_adaptive.
+struct ProfileEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
+inline ProfileEvents& profile_events() {
+  static thread_local ProfileEvents ev;
+  return ev;
+}
+
 // Compute units of the current device (queried once per device).
 inline int device_cus() {
   static std::atomic<int> cached[64];
