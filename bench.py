@@ -76,6 +76,23 @@ def measured_traffic(kernel_tag, digest):
         return None
 
 
+def measured_valu(kernel_tag, digest):
+    """VALU instructions per 64-pair wavefront row from the committed rocprofv3 SQ counter
+    summary of this kernel, or None when absent or taken from other sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_sq.md")
+    if not os.path.exists(path):
+        return None
+    got = dict(re.findall(r"^- (\w+): `([^`]+)`", open(path).read(), re.M))
+    if got.get("source_sha256") != digest:
+        return None
+    try:
+        return {"valu_per_row": float(got["valu_insts_per_row"]),
+                "fp64_per_row": float(got["fp64_insts_per_row"]),
+                "source": os.path.relpath(path, ROOT)}
+    except (KeyError, ValueError):
+        return None
+
+
 def run_mode(torch, sphint, call, nnz, mode, steps, warmup):
     """Times `steps` calls of call(out, mode) (one sphint_arc_constlat each)."""
     out = sphint.Output(nnz)
@@ -119,6 +136,14 @@ def roofline(mode, r, pairs, bytes_launch, kernel, tag):
     roof["traffic"] = tr["bytes"] if tr else None
     if tr:
         roof["traffic_detail"] = tr
+    va = measured_valu(tag, source_digest()) if tag else None
+    if va:  # the measured issue roof: wavefront VALU instructions x 64 lanes per launch
+        lane_instr = va["valu_per_row"] * 64 * (pairs / 64)
+        rate = lane_instr / (kms * 1e-3)
+        roof["valu_issue"] = {"achieved": rate / 1e12, "peak": ALU_PEAK / 1e12,
+                              "unit": "Tlane-instr/s", "frac": rate / ALU_PEAK,
+                              "valu_instr_per_pair": va["valu_per_row"],
+                              "fp64_instr_per_pair": va["fp64_per_row"], "source": va["source"]}
     roof["kernel"] = kernel
     roof["kernel_ms"] = kms
     roof["kernel_ms_p10_p50_p90"] = pctl(r["kernel_ms"])
