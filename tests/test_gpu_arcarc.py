@@ -207,3 +207,37 @@ def test_full_size_shared_vertex_property(full):
     v = v / np.linalg.norm(v, axis=1, keepdims=True)
     err = np.max(np.abs(np.stack([x, y, z], axis=1) - v))
     assert err <= 6 * U, err / U  # 4 u for the point, 2 u for numpy's normalisation
+
+
+def test_full_size_accuracy_by_part(full):
+    """Printed table: per part of the 1e7 workload, on 500 sampled pairs, the naive and EFT
+    max-norm point errors against the exact point (units of 2^-53, over pairs both the exact
+    rule and the evaluation call hits) and how often each evaluation's hit count differs from
+    the exact one."""
+    from decimal import Decimal
+    from oracle import arcarc as AA
+    P, A, B, eft, naive = full
+    g = np.random.Generator(np.random.PCG64(99))
+    names = ("crossing", "short", "parallel", "shared vertex")
+    print("\n[gpu-arcarc] part: naive err median / max, count mismatches | eft err median / max, count mismatches")
+    for k, name in enumerate(names):
+        sel = g.choice(np.nonzero(P.part == k)[0], 500, replace=False)
+        stats = {}
+        for label, res in (("naive", naive), ("eft", eft)):
+            errs, miss = [], 0
+            for i in sel:
+                a1, a2, b1, b2 = (tuple(float(x) for x in v[i]) for v in (P.a1, P.a2, P.b1, P.b2))
+                c, sg, _ = AA.classify(a1, a2, b1, b2)
+                got = int(res[0][i])
+                miss += got != c
+                if c and got:
+                    p = AA.point(a1, a2, b1, b2, sg)
+                    q = (float(res[2][i]), float(res[3][i]), float(res[4][i]))
+                    errs.append(float(max(abs(Decimal(v) - w) for v, w in zip(q, p)) / Decimal(U)))
+            stats[label] = (float(np.median(errs)) if errs else 0.0, max(errs) if errs else 0.0, miss)
+        (nm, nx, nmis), (em, ex, emis) = stats["naive"], stats["eft"]
+        print(f"[gpu-arcarc] {name:13s}: {nm:.3g} / {nx:.3g}, {nmis} | {em:.3g} / {ex:.3g}, {emis}",
+              flush=True)
+        assert emis == 0 and ex <= 4.0
+        if name == "shared vertex":
+            assert nmis > 100
