@@ -190,3 +190,27 @@ def test_exact_orient_against_integers(hc):
         assert got == want, (u, v, w)
         zeros += want == 0
     assert zeros >= 400
+
+
+def test_reversal_and_swap_invariance(hc):
+    """Reversing either arc or swapping the two arcs negates n_A x n_B and the decision sign
+    together, so the reported point is the same; the EFT arithmetic is antisymmetric exactly
+    (TwoSum and TwoProduct commute with negation), so the outputs agree bit for bit, and the
+    exact oracle agrees on the counts."""
+    pairs = special_pairs()[:9] + as_tuples(inputs.arc_pairs(800, seed_tag=63))
+    a, b = soa(pairs)
+    base = run(hc, 1, a, b)
+    variants = {
+        "reverse A": (a[3:] + a[:3], b),
+        "reverse B": (a, b[3:] + b[:3]),
+        "swap": (b, a),
+    }
+    base_naive = run(hc, 0, a, b)
+    for name, (va, vb) in variants.items():
+        for mode, ref in ((1, base), (0, base_naive)):
+            got = run(hc, mode, va, vb)
+            for g_, r_ in zip(got, ref):
+                assert np.array_equal(g_, r_, equal_nan=True), (name, mode)
+    for a1, a2, b1, b2 in pairs[:200]:
+        assert AA.classify(a2, a1, b1, b2)[0] == AA.classify(a1, a2, b1, b2)[0]
+        assert AA.classify(b1, b2, a1, a2)[0] == AA.classify(a1, a2, b1, b2)[0]
