@@ -216,3 +216,34 @@ def test_eft_heights_near_pole_within_ulps(hc):
     a = np.array(rows)
     soa = [a[:, k].copy() for k in range(7)]
     compare_eft(hc, soa)
+
+
+@pytest.mark.parametrize("mode", [1, 0])
+def test_metamorphic_relations_bit_exact(hc, mode):
+    """Swapping the endpoints reverses the hits and exchanges their labels; mirroring z
+    exchanges the labels in place; scaling an endpoint by 8 changes nothing (EFT only: the
+    naive mode compares z0 with raw endpoint heights).  Points agree bit for bit: the
+    arithmetic commutes with negation and with scaling by powers of two.  A tangency's double
+    root may carry either label."""
+    for P in (inputs.ill_conditioned(20000, seed_tag=31), inputs.uniform_arcs(20000, seed_tag=32)):
+        x1, y1, z1, x2, y2, z2, z0 = P.soa()
+        cnt, fl, r0, r1, px0, py0, px1, py1 = run(hc, mode, (x1, y1, z1, x2, y2, z2, z0))
+        nt = (fl & 2) == 0
+        one, two, hit = cnt == 1, cnt == 2, cnt > 0
+        c2, f2, s0, s1, qx0, qy0, qx1, qy1 = run(hc, mode, (x2, y2, z2, x1, y1, z1, z0))
+        assert np.array_equal(cnt, c2) and np.array_equal(fl, f2)
+        assert np.array_equal(px0[one], qx0[one]) and np.array_equal(py0[one], qy0[one])
+        assert np.array_equal(r0[one & nt], 1 - s0[one & nt])
+        assert np.array_equal(px0[two], qx1[two]) and np.array_equal(px1[two], qx0[two])
+        assert np.array_equal(py0[two], qy1[two]) and np.array_equal(py1[two], qy0[two])
+        assert np.array_equal(r0[two], 1 - s1[two]) and np.array_equal(r1[two], 1 - s0[two])
+        c3, f3, m0, m1, mx0, my0, mx1, my1 = run(hc, mode, (x1, y1, -z1, x2, y2, -z2, -z0))
+        assert np.array_equal(cnt, c3) and np.array_equal(fl, f3)
+        assert np.array_equal(px0[hit], mx0[hit]) and np.array_equal(py0[hit], my0[hit])
+        assert np.array_equal(px1[two], mx1[two]) and np.array_equal(py1[two], my1[two])
+        assert np.array_equal(r0[hit & nt], 1 - m0[hit & nt])
+        assert np.array_equal(r1[two], 1 - m1[two])
+        if mode == 1:
+            scaled = run(hc, mode, (8 * x1, 8 * y1, 8 * z1, x2, y2, z2, z0))
+            for u, v in zip((cnt, fl, r0, r1, px0, py0, px1, py1), scaled):
+                assert np.array_equal(u, v)
