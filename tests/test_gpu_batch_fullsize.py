@@ -1,0 +1,142 @@
+"""GPU: the batched launch at the full 64-mesh size, against per-mesh calls and the oracle.
+
+64 meshes with log-uniform 1e3..1e7 arcs (arc length U[1e-3, 0.05] rad) and U{10..3600}
+uniformly spaced latitudes, as the batch benchmark draws them, about 8e8 candidate pairs.
+The arcs are drawn on the device (torch's seeded generator) and the CSR lists are built by
+the library's own candidate kernels, so the whole set is ready in seconds; the benchmark's
+host-built lists differ only by extra edge candidates.  Checks, in the benchmark's launch
+configuration (one autotuned persistent graph launch):
+
+* every mesh's output equals that mesh's single call bit for bit (compared on the device);
+* 400 pairs sampled across the meshes match the exact oracle (counts, roots, flags) and the
+  AccuX replica (points, within 4 * 2^-53).
+"""
+
+import math
+from decimal import Decimal
+
+import numpy as np
+import pytest
+
+from oracle import batch as OB
+from paper_2510_09892_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+def note(msg):
+    print(f"[gpu-batch-full] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+def device_arcs(torch, gen, n, d_lo=1e-3, d_hi=0.05):
+    """p1 uniform on the sphere, p2 at distance d ~ U[d_lo, d_hi] along a uniform bearing."""
+    f64 = dict(dtype=torch.float64, device="cuda")
+    p = torch.randn(n, 3, generator=gen, **f64)
+    p = p / p.norm(dim=1, keepdim=True)
+    d = d_lo + (d_hi - d_lo) * torch.rand(n, generator=gen, **f64)
+    b = 2 * math.pi * torch.rand(n, generator=gen, **f64)
+    x, y, z = p[:, 0], p[:, 1], p[:, 2]
+    r = torch.hypot(x, y)
+    east = torch.stack([-y / r, x / r, torch.zeros_like(r)], dim=1)
+    north = torch.stack([-z * x / r, -z * y / r, r], dim=1)
+    t = torch.cos(b)[:, None] * north + torch.sin(b)[:, None] * east
+    q = torch.cos(d)[:, None] * p + torch.sin(d)[:, None] * t
+    return [p[:, k].contiguous() for k in range(3)], [q[:, k].contiguous() for k in range(3)]
+
+
+@pytest.fixture(scope="module")
+def meshes(torch_cuda):
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    g = inputs.rng(3)
+    sizes = np.floor(np.exp(g.uniform(np.log(1e3), np.log(1e7), 64))).astype(int)
+    lats = g.integers(10, 3601, 64)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(inputs.SEED_BASE + 3)
+    out = []
+    for k, (n, L) in enumerate(zip(sizes, lats)):
+        p1, p2 = device_arcs(torch, gen, int(n))
+        step = 180.0 / int(L)
+        lat_z = torch.from_numpy(inputs.latitude_lines(int(L), -90.0 + step / 2, step)).cuda()
+        off, idx = sphint.candidates(tuple(p1), tuple(p2), lat_z)
+        out.append(dict(p1=tuple(p1), p2=tuple(p2), lat_z=lat_z, lat_offsets=off, lat_idx=idx,
+                        out=sphint.Output(len(idx))))
+    torch.cuda.synchronize()
+    note(f"64 meshes: {int(sizes.sum())} arcs, {sum(len(m['lat_idx']) for m in out)} pairs")
+    return out
+
+
+@pytest.mark.parametrize("mode", ["eft", "naive"])
+def test_full_batch_equals_per_mesh_and_sampled_oracle(torch_cuda, meshes, mode):
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    plan = sphint.BatchPlan(meshes, mode=mode)
+    try:
+        plan.autotune()
+        note(f"{mode}: autotuned params {plan.params()}")
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.check()
+    finally:
+        plan.close()
+    biggest = max(len(m["lat_idx"]) for m in meshes)
+    scratch = sphint.Output(biggest)
+    g = np.random.Generator(np.random.PCG64(33))
+    picks = []
+    for k, m in enumerate(meshes):
+        nnz = len(m["lat_idx"])
+        o = m["out"]
+        ref = sphint.Output(nnz) if nnz != biggest else scratch
+        sphint.arc_constlat(m["p1"], m["p2"], m["lat_z"], m["lat_offsets"], m["lat_idx"],
+                            mode=mode, out=ref)
+        torch.cuda.synchronize()
+        t = ref.check()
+        assert int(o.total.item()) == t, k
+        assert torch.equal(o.count, ref.count) and torch.equal(o.flags, ref.flags), k
+        for a, b in ((o.x, ref.x), (o.y, ref.y), (o.pair, ref.pair), (o.root, ref.root)):
+            assert torch.equal(a[:t], b[:t]), k
+        if mode == "eft" and nnz:
+            picks += [(k, int(q)) for q in g.integers(0, nnz, 7)]
+    note(f"{mode}: every mesh equals its single call")
+    if mode != "eft":
+        return
+    # sampled pairs against the oracle
+    rows, hits = [], []
+    for k, q in picks[:400]:
+        m = meshes[k]
+        qt = torch.tensor([q], dtype=torch.int64, device="cuda")
+        arc = int(torch.searchsorted(m["lat_offsets"], qt, right=True).item()) - 1
+        lat = int(m["lat_idx"][q].item())
+        x1 = tuple(float(c[arc].item()) for c in m["p1"])
+        x2 = tuple(float(c[arc].item()) for c in m["p2"])
+        z0 = float(m["lat_z"][lat].item())
+        o = m["out"]
+        first = int(o.count[:q].sum().item())
+        c = int(o.count[q].item())
+        hits.append((c, int(o.flags[q].item()), o.x[first:first + c].cpu().numpy(),
+                     o.y[first:first + c].cpu().numpy(), o.root[first:first + c].cpu().numpy()))
+        rows.append((*x1, *x2, z0))
+    soa = [np.array([r[i] for r in rows]) for i in range(7)]
+    ex = OB.exact(*soa, workers=1)
+    rep = OB.accux_points(*soa, ex.roots, workers=1)
+    k = 0
+    for i, (c, fl, xs, ys, rs) in enumerate(hits):
+        assert c == ex.count[i] and (fl & 31) == ex.flags[i], i
+        assert tuple(int(r) for r in rs) == ex.roots[i], i
+        for j in range(c):
+            assert (xs[j], ys[j]) == rep[i][j], (i, j)
+            e = max(abs(Decimal(float(xs[j])) - ex.hit_x[k]),
+                    abs(Decimal(float(ys[j])) - ex.hit_y[k])) / Decimal(U)
+            assert e <= 4, (i, j, float(e))
+            k += 1
+    note(f"{len(hits)} sampled pairs match the oracle")
