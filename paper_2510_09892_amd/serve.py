@@ -163,9 +163,11 @@ class Server:
     def run(self, arrivals, payload_of, keep_outputs=False, check_every=0):
         """Serves requests i = 0..len(arrivals)-1 arriving at ``arrivals[i]`` seconds after
         the start; ``payload_of(i)`` gives request i's Payload.  Returns a report dict (and
-        the outputs by request id when ``keep_outputs``).  ``check_every`` = k > 0 also reads
-        back the hit total and error word of every k-th request."""
+        the outputs by request id when ``keep_outputs``: True keeps every request's, a
+        callable keeps those of the ids it accepts).  ``check_every`` = k > 0 also reads back
+        the hit total and error word of every k-th request."""
         torch = self.torch
+        keep = keep_outputs if callable(keep_outputs) else (lambda rid: bool(keep_outputs))
         n = len(arrivals)
         for p in {id(payload_of(i)): payload_of(i) for i in range(n)}.values():
             if p.footprint > self.budget:
@@ -202,10 +204,11 @@ class Server:
                     lat_nocopy.append(t_done - arrivals[rid] - c)
                     h2d.append(c)
                     pairs += p.nnz
-                    if keep_outputs or (check_every and rid % check_every == 0):
+                    kept = keep(rid)
+                    if kept or (check_every and rid % check_every == 0):
                         r = self._collect(s)
                         hits += r["total"]
-                        if keep_outputs:
+                        if kept:
                             outputs[rid] = r
                     s.rid = s.payload = None
                     done += 1

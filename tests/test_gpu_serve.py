@@ -5,6 +5,9 @@
 * Launches on different streams at once give the results of the same launches run one
   after the other (the library orders its launches on the device).
 * A few served requests are checked against the oracle.
+* At the serving configuration's own rate (Poisson, 2000 requests/s, requests of
+  log-uniform 1e3..1e6 arcs x 1..1000 latitudes, 64 GiB budget, 8 slots), a sample of the
+  served requests equals the same requests run alone.
 """
 
 import sys
@@ -122,3 +125,28 @@ def test_concurrent_streams_equal_serial(torch_cuda):
         assert o.check() == t
         assert np.array_equal(o.count.cpu().numpy(), c)
         assert np.array_equal(o.x[:t].cpu().numpy().view(np.uint8), x.view(np.uint8))
+
+
+@pytest.mark.parametrize("mode", ["eft", "naive"])
+def test_full_rate_stream_sampled_equals_alone(torch_cuda, mode):
+    from paper_2510_09892_amd import serve
+    torch = torch_cuda
+    _, specs = inputs.request_stream(seed_tag=4, max_requests=16)
+    note(f"building 16 request meshes ({mode})")
+    meshes = [inputs.random_mesh(inputs.rng(4, seed), n_arcs, n_lat) for n_arcs, n_lat, seed in specs]
+    pool = [serve.Payload(m) for m in meshes]
+    arrivals, _ = inputs.request_stream(rate_hz=2000.0, duration_s=2.0, seed_tag=4)
+    srv = serve.Server(mode=mode, budget_bytes=64 << 30, slots=8)
+    note(f"serving {len(arrivals)} requests at 2000/s")
+    rep, outs = srv.run(arrivals, lambda i: pool[i % len(pool)],
+                        keep_outputs=lambda rid: rid % 53 == 0)
+    srv.close()
+    note(f"served: {rep['req_per_s']:.0f} req/s, p99 {rep['latency_ms']['p99']:.3f} ms, "
+         f"{len(outs)} outputs kept")
+    assert rep["requests"] == len(arrivals) and len(outs) == (len(arrivals) + 52) // 53
+    ref = {}
+    for rid, r in outs.items():
+        k = rid % len(pool)
+        if k not in ref:
+            ref[k] = alone(torch, meshes[k], mode)
+        assert same_bytes(r, ref[k]), (rid, k)
