@@ -46,17 +46,14 @@ struct NormalPairs {
 __host__ __device__ __forceinline__ NormalPairs normal_pairs(double ux, double uy, double uz,
                                                              double vx, double vy, double vz) {
   NormalPairs r;
-  const double a[3] = {uy, uz, ux}, b[3] = {vz, vx, vy}, c[3] = {uz, ux, uy}, d[3] = {vy, vz, vx};
+  const dop3 c[3] = {accu_dop(uy, vz, uz, vy), accu_dop(uz, vx, ux, vz), accu_dop(ux, vy, uy, vx)};
   bool zero = true;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const dd p1 = two_prod(a[i], b[i]), p2 = two_prod(c[i], d[i]);
-    zero = zero && p1.hi == p2.hi && p1.lo == p2.lo;
-    const dd t = two_sum(p1.hi, -p2.hi);
-    const dd n = two_sum(t.hi, t.lo + (p1.lo - p2.lo));
-    r.n[i] = n.hi;
-    r.e[i] = n.lo;
-    r.m[i] = __builtin_fabs(p1.hi) + __builtin_fabs(p2.hi);
+    zero = zero && c[i].zero;
+    r.n[i] = c[i].hi;
+    r.e[i] = c[i].lo;
+    r.m[i] = c[i].mag;
   }
   r.zero = zero;
   return r;

@@ -44,7 +44,8 @@ __host__ __device__ __forceinline__ int sgn(double v) { return (v > 0.0) - (v < 
 // identity a*b - c*d = (p1 - p2) + (r1 - r2)), followed by a TwoSum renormalisation so that
 // |lo| <= u |hi|; mag = |p1| + |p2| bounds the compensation error (3.01 u^2 mag).
 struct dop3 {
-  double hi, lo, mag;
+  double hi, lo, mag;  // the renormalised pair and |p1| + |p2|
+  bool zero;           // a*b - c*d == 0 exactly: both TwoProducts agree in both parts
 };
 __host__ __device__ __forceinline__ dop3 accu_dop(double a, double b, double c, double d) {
   dd p1 = two_prod(a, b);
@@ -52,7 +53,8 @@ __host__ __device__ __forceinline__ dop3 accu_dop(double a, double b, double c, 
   dd t = two_sum(p1.hi, -p2.hi);
   double err = t.lo + (p1.lo - p2.lo);
   dd n = two_sum(t.hi, err);
-  return {n.hi, n.lo, __builtin_fabs(p1.hi) + __builtin_fabs(p2.hi)};
+  return {n.hi, n.lo, __builtin_fabs(p1.hi) + __builtin_fabs(p2.hi),
+          p1.hi == p2.hi && p1.lo == p2.lo};
 }
 
 // Alg. 6 (SumNonNeg).  Its leading TwoSum adds two non-negative numbers, so it is done as

@@ -191,38 +191,20 @@ __host__ __device__ __forceinline__ void arc_eft(double x1, double y1, double z1
   }
   // Alg. 8 lines 2-4 (normal n = x1 x x2).  A component is exactly zero iff both
   // TwoProducts agree in both parts (fl(x) and x - fl(x) determine x).
-  dd px1 = two_prod(y1, z2), px2 = two_prod(z1, y2);
-  dd py1 = two_prod(z1, x2), py2 = two_prod(x1, z2);
-  dd pz1 = two_prod(x1, y2), pz2 = two_prod(y1, x2);
-  bool zx = px1.hi == px2.hi && px1.lo == px2.lo;
-  bool zy = py1.hi == py2.hi && py1.lo == py2.lo;
-  bool zz = pz1.hi == pz2.hi && pz1.lo == pz2.lo;
-  if (zx && zy && zz) {
+  const dop3 nx = accu_dop(y1, z2, z1, y2);
+  const dop3 ny = accu_dop(z1, x2, x1, z2);
+  const dop3 nz = accu_dop(x1, y2, y1, x2);
+  if (nx.zero && ny.zero && nz.zero) {
     a.flags = F_DEGEN_N;
     return;
   }
-  if (zx && zy) {
+  if (nx.zero && ny.zero) {
     a.flags = F_HORIZ;
     return;
   }
-  {
-    dd t = two_sum(px1.hi, -px2.hi);
-    dd n = two_sum(t.hi, t.lo + (px1.lo - px2.lo));
-    a.nx = n.hi; a.enx = n.lo;
-    a.mx = __builtin_fabs(px1.hi) + __builtin_fabs(px2.hi);
-  }
-  {
-    dd t = two_sum(py1.hi, -py2.hi);
-    dd n = two_sum(t.hi, t.lo + (py1.lo - py2.lo));
-    a.ny = n.hi; a.eny = n.lo;
-    a.my = __builtin_fabs(py1.hi) + __builtin_fabs(py2.hi);
-  }
-  {
-    dd t = two_sum(pz1.hi, -pz2.hi);
-    dd n = two_sum(t.hi, t.lo + (pz1.lo - pz2.lo));
-    a.nz = n.hi; a.enz = n.lo;
-    a.mz = __builtin_fabs(pz1.hi) + __builtin_fabs(pz2.hi);
-  }
+  a.nx = nx.hi; a.enx = nx.lo; a.mx = nx.mag;
+  a.ny = ny.hi; a.eny = ny.lo; a.my = ny.mag;
+  a.nz = nz.hi; a.enz = nz.lo; a.mz = nz.mag;
   norms(a);  // Alg. 8 lines 5-6
   dd fx = f_pair(a.nx, a.enx, a.nz, a.enz);
   dd fy = f_pair(a.ny, a.eny, a.nz, a.enz);
