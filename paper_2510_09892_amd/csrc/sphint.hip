@@ -15,9 +15,11 @@ namespace {
 
 // Clears the tile states, counter and error word; writes *ototal = 0 for empty calls; for
 // CSR calls (off != NULL) also writes the pair-to-arc table (one launch for both).
-__global__ void k_init(uint32_t* ws, uint64_t* status, int64_t ntiles, int64_t* ototal,
-                       int64_t nnz, const int64_t* __restrict__ off, int64_t n_arcs,
-                       uint32_t* __restrict__ parc) {
+__global__ __launch_bounds__(INIT_BLOCK) void k_init(uint32_t* ws, uint64_t* status,
+                                                     int64_t ntiles, int64_t* ototal, int64_t nnz,
+                                                     const int64_t* __restrict__ off,
+                                                     int64_t n_arcs,
+                                                     uint32_t* __restrict__ parc) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     ws[0] = 0u;
@@ -25,19 +27,23 @@ __global__ void k_init(uint32_t* ws, uint64_t* status, int64_t ntiles, int64_t* 
     if (nnz == 0) *ototal = 0;
   }
   for (int64_t k = t; k < ntiles; k += (int64_t)gridDim.x * blockDim.x) status[k] = 0ull;
+  __shared__ uint32_t win[INIT_BLOCK / 64][FILL_W];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (off && nnz > 0)
-    fill_pair_arcs(off, n_arcs, nnz, parc,
-                   (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6),
-                   (int64_t)gridDim.x * (blockDim.x / 64));
+    fill_pair_arcs(off, n_arcs, nnz, parc, (int64_t)blockIdx.x * (INIT_BLOCK / 64) + wave,
+                   (int64_t)gridDim.x * (INIT_BLOCK / 64), win[wave]);
 }
 
 }  // namespace
 
 namespace sphint {
-__global__ void k_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs, int64_t nnz,
-                            uint32_t* __restrict__ parc) {
-  fill_pair_arcs(off, n_arcs, nnz, parc, (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6),
-                 (int64_t)gridDim.x * (blockDim.x / 64));
+__global__ __launch_bounds__(INIT_BLOCK) void k_pair_arcs(const int64_t* __restrict__ off,
+                                                          int64_t n_arcs, int64_t nnz,
+                                                          uint32_t* __restrict__ parc) {
+  __shared__ uint32_t win[INIT_BLOCK / 64][FILL_W];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  fill_pair_arcs(off, n_arcs, nnz, parc, (int64_t)blockIdx.x * (INIT_BLOCK / 64) + wave,
+                 (int64_t)gridDim.x * (INIT_BLOCK / 64), win[wave]);
 }
 }  // namespace sphint
 
@@ -110,12 +116,13 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
   LaunchChain chain;
   if (chain.begin(st) != hipSuccess) return SPHINT_E_HIP;
   uint32_t* parc = (uint32_t*)((char*)workspace + WS_HEADER + 8 * status_words_for(nnz));
-  int64_t init_threads = ntiles > 0 ? ntiles : 1;
-  if (lat_offsets && n_arcs > init_threads) init_threads = n_arcs;  // one lane per arc
-  int64_t init_blocks = (init_threads + 255) / 256;
+  int64_t init_blocks = (ntiles + INIT_BLOCK - 1) / INIT_BLOCK;  // one lane per tile state
   if (init_blocks > 8192) init_blocks = 8192;
-  hipLaunchKernelGGL(k_init, dim3((unsigned)init_blocks), dim3(256), 0, st, ws, status, ntiles,
-                     out_total, nnz, lat_offsets, n_arcs, parc);
+  if (lat_offsets && nnz > 0 && fill_blocks(n_arcs) > init_blocks)
+    init_blocks = fill_blocks(n_arcs);
+  if (init_blocks < 1) init_blocks = 1;
+  hipLaunchKernelGGL(k_init, dim3((unsigned)init_blocks), dim3(INIT_BLOCK), 0, st, ws, status,
+                     ntiles, out_total, nnz, lat_offsets, n_arcs, parc);
   if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
   if (nnz == 0) return chain.end() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
 

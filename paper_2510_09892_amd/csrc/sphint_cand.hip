@@ -2,7 +2,8 @@
 //
 // Two calls on one stream and one workspace:
 //   sphint_candidates_count: per arc, the first candidate latitude and the count (one lane
-//     per arc; the latitude table is staged in LDS when it fits), per-block sums, one
+//     per arc; the latitude table is staged in LDS, sized to it, when it has at most
+//     LDS_LAT entries; both ends found by one lockstep binary search), per-block sums, one
 //     block scanning the block sums, then every block writing its exclusive prefixes into
 //     lat_offsets and the last one the total;
 //   sphint_candidates_fill: lat_idx, written by wavefronts that take 64 arcs at a time and
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(CB) void k_cand_count(const double* __restrict__ x1
                                                    const double* __restrict__ z2,
                                                    int64_t n_arcs, const double* __restrict__ lat_z,
                                                    int32_t n_lat, double pad, CandWs w) {
-  __shared__ double lz[LDS_LAT];
+  extern __shared__ double lz[];  // n_lat entries when staged (sized at launch)
   __shared__ int64_t red[CB / 64];
   const bool staged = n_lat <= LDS_LAT;
   if (staged)
@@ -205,7 +206,9 @@ extern "C" sphint_status sphint_candidates_count(int64_t n_arcs, sphint_pts_soa 
   const int64_t nb = cand_blocks(n_arcs);
   if (nb > 0x7fffffffLL) return SPHINT_E_INVAL;
   if (nb > 0) {
-    hipLaunchKernelGGL(k_cand_count, dim3((unsigned)nb), dim3(CB), 0, st, p1.x, p1.y, p1.z,
+    // the latitude table in LDS only as large as it is: more workgroups fit on a CU
+    const size_t lds = n_lat <= LDS_LAT ? 8 * (size_t)n_lat : 0;
+    hipLaunchKernelGGL(k_cand_count, dim3((unsigned)nb), dim3(CB), lds, st, p1.x, p1.y, p1.z,
                        p2.x, p2.y, p2.z, n_arcs, lat_z, (int32_t)n_lat, pad, w);
     if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
   }

@@ -44,26 +44,22 @@ __host__ __device__ __forceinline__ ZRange arc_zrange(double x1, double y1, doub
   return {lo - eps, hi + eps};
 }
 
-// First index k of the ascending table z[0..n) with z[k] >= v (n if none).
-__host__ __device__ __forceinline__ int32_t lower_index(const double* z, int32_t n, double v) {
-  int32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (z[mid] < v) lo = mid + 1;
-    else hi = mid;
+// Both ends of the candidate range in the ascending table z[0..n), n >= 1: first = the
+// first index k with z[k] >= lo, end = the first index k with z[k] > hi (n if none).  The two
+// binary searches run in lockstep with a fixed number of halvings (ceil(log2 n)), so their
+// loads are independent and every lane of a wavefront takes the same trip count.
+__host__ __device__ __forceinline__ void candidate_span(const double* z, int32_t n, double lo,
+                                                        double hi, int32_t& first,
+                                                        int32_t& end) {
+  int32_t b1 = 0, b2 = 0, len = n;  // the answers lie in [b, b + len]
+  while (len > 1) {
+    const int32_t half = len >> 1;
+    b1 = z[b1 + half] < lo ? b1 + half : b1;
+    b2 = z[b2 + half] <= hi ? b2 + half : b2;
+    len -= half;
   }
-  return lo;
-}
-
-// First index k of the ascending table z[0..n) with z[k] > v (n if none).
-__host__ __device__ __forceinline__ int32_t upper_index(const double* z, int32_t n, double v) {
-  int32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (z[mid] <= v) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
+  first = b1 + (z[b1] < lo ? 1 : 0);
+  end = b2 + (z[b2] <= hi ? 1 : 0);
 }
 
 // The arc's candidates: latitudes [first, first + count) of the ascending table.
@@ -72,13 +68,13 @@ __host__ __device__ __forceinline__ void arc_candidates(double x1, double y1, do
                                                         int32_t n_lat, double pad,
                                                         int32_t& first, int32_t& count) {
   const ZRange r = arc_zrange(x1, y1, z1, x2, y2, z2, pad);
-  if (!(r.lo <= r.hi)) {
+  if (!(r.lo <= r.hi) || n_lat <= 0) {
     first = 0;
     count = 0;
     return;
   }
-  first = lower_index(lat_z, n_lat, r.lo);
-  const int32_t end = upper_index(lat_z, n_lat, r.hi);
+  int32_t end;
+  candidate_span(lat_z, n_lat, r.lo, r.hi, first, end);
   count = end > first ? end - first : 0;
 }
 

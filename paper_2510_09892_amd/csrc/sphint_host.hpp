@@ -60,17 +60,26 @@ inline size_t workspace_bytes_for(int64_t nnz) {
   return WS_HEADER + 8 * status_words_for(nnz) + 4 * (size_t)(nnz > 0 ? nnz : 0);
 }
 
-// One thread per arc (grid-stride): the CSR pair-to-arc table.
+// Workgroup size of the init and pair-to-arc launches.
+constexpr int INIT_BLOCK = 256;
+
+// Workgroups for the pair-to-arc table of n_arcs arcs: one lane per FILL_G arcs, capped
+// (the fill loops over the rest).
+inline int64_t fill_blocks(int64_t n_arcs) {
+  const int64_t lanes = (n_arcs + FILL_G - 1) / FILL_G;
+  const int64_t b = (lanes + INIT_BLOCK - 1) / INIT_BLOCK;
+  return b > 8192 ? 8192 : (b < 1 ? 1 : b);
+}
+
+// The CSR pair-to-arc table (fill_pair_arcs) as a launch of its own.
 __global__ void k_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs, int64_t nnz,
                             uint32_t* __restrict__ parc);
 
 inline hipError_t launch_pair_arcs(const int64_t* off, int64_t n_arcs, int64_t nnz,
                                    uint32_t* parc, hipStream_t st) {
   if (n_arcs <= 0 || nnz <= 0) return hipSuccess;
-  int64_t blocks = (n_arcs + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_pair_arcs, dim3((unsigned)blocks), dim3(256), 0, st, off, n_arcs, nnz,
-                     parc);
+  hipLaunchKernelGGL(k_pair_arcs, dim3((unsigned)fill_blocks(n_arcs)), dim3(INIT_BLOCK), 0, st,
+                     off, n_arcs, nnz, parc);
   return hipGetLastError();
 }
 

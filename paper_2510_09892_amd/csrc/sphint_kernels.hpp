@@ -302,36 +302,58 @@ __device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int 
   return r;
 }
 
-// CSR pair-to-arc table: parc[k] = the arc owning entry k.  Wavefront w of nw takes 64
-// consecutive arcs at a time (their offsets read once, coalesced).  The entries of those
-// arcs form one run, which the 64 lanes write together (coalesced): each entry finds its
-// arc by a binary search over the 64 arcs' first entries, held one per lane.  Entries are
-// written only inside [0, nnz) and only by the arc whose range holds them, so malformed
-// offsets leave entries unwritten (clamped where they are read) but never write out of
-// bounds.
+// CSR pair-to-arc table: parc[k] = the arc owning entry k.  Wavefront w of nw takes
+// FILL_G * 64 consecutive arcs at a time and issues all their offset loads together
+// (coalesced), so a wavefront waits for memory once per FILL_G groups of 64 arcs.  The
+// entries of one group form one run [lo, hi); a window of FILL_W entries moves along it:
+// every lane writes its own arc's entries inside the window into the wavefront's LDS
+// buffer `win`, and the wavefront copies the window out with coalesced stores.  With
+// monotone offsets the lanes' entries tile the window exactly.  Stores stay inside
+// [lo, hi), clamped to [0, nnz), and LDS indices inside the window, so malformed
+// offsets leave wrong arc ids in the table (clamped where they are read) but never
+// reach outside either buffer.
+constexpr int FILL_G = 4;    // groups of 64 arcs per load batch
+constexpr int FILL_W = 512;  // window entries per wavefront (2 KB of LDS)
+
 __device__ __forceinline__ void fill_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs,
                                                int64_t nnz, uint32_t* __restrict__ parc,
-                                               int64_t w, int64_t nw) {
+                                               int64_t w, int64_t nw, uint32_t* win) {
   const int lane = __lane_id();
-  for (int64_t a0 = w * 64; a0 < n_arcs; a0 += nw * 64) {  // wavefront-uniform loop
-    const int64_t a = a0 + lane;
-    const bool ok = a < n_arcs;
-    int64_t b = ok ? off[a] : nnz, e = ok ? off[a + 1] : nnz;
-    b = b < 0 ? 0 : (b > nnz ? nnz : b);
-    e = e < b ? b : (e > nnz ? nnz : e);
-    const int last = n_arcs - a0 < 64 ? (int)(n_arcs - a0) - 1 : 63;
-    const int64_t lo = __shfl(b, 0, 64);
-    const int64_t hi = __shfl(e, last, 64);
-    for (int64_t q0 = lo; q0 < hi; q0 += 64) {
-      const int64_t q = q0 + lane;
-      int l = 0;  // largest lane with b <= q (lane 0's b = lo <= q)
+  for (int64_t a0 = w * 64 * FILL_G; a0 < n_arcs; a0 += nw * 64 * FILL_G) {  // uniform
+    int64_t b[FILL_G], e[FILL_G];
 #pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        const int64_t bc = __shfl(b, l + step, 64);
-        if (bc <= q) l += step;
+    for (int g = 0; g < FILL_G; ++g) {  // n_arcs >= 1 here, so the clamped index is valid
+      const int64_t a = a0 + g * 64 + lane;
+      const int64_t ac = a < n_arcs ? a : n_arcs - 1;
+      b[g] = off[ac];
+      e[g] = off[ac + 1];
+    }
+#pragma unroll
+    for (int g = 0; g < FILL_G; ++g) {
+      const int64_t ga = a0 + g * 64;
+      if (ga >= n_arcs) break;  // wavefront-uniform
+      const int64_t a = ga + lane;
+      const bool ok = a < n_arcs;
+      int64_t bb = ok ? b[g] : nnz, ee = ok ? e[g] : nnz;
+      bb = bb < 0 ? 0 : (bb > nnz ? nnz : bb);
+      ee = ee < bb ? bb : (ee > nnz ? nnz : ee);
+      const int last = n_arcs - ga < 64 ? (int)(n_arcs - ga) - 1 : 63;
+      const int64_t lo = __shfl(bb, 0, 64);
+      const int64_t hi = __shfl(ee, last, 64);
+      for (int64_t w0 = lo; w0 < hi; w0 += FILL_W) {  // wavefront-uniform
+        const int64_t w1 = hi - w0 < FILL_W ? hi : w0 + FILL_W;
+        const int64_t s = bb > w0 ? bb : w0;
+        const int64_t t = ee < w1 ? ee : w1;
+        for (int64_t q = s; q < t; ++q) win[(uint32_t)(q - w0) & (FILL_W - 1)] = (uint32_t)a;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int n = (int)(w1 - w0);
+        for (int k = lane; k < n; k += 64) parc[w0 + k] = win[k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      const int64_t el = __shfl(e, l, 64);
-      if (q < hi && q < el) parc[q] = (uint32_t)(a0 + l);
     }
   }
 }

@@ -205,6 +205,35 @@ def test_csr_cubed_sphere_small(torch_cuda):
     check_eft(res, m.expand().soa())
 
 
+def concat_meshes(parts):
+    """One CSR mesh from meshes that share a latitude table (empty parts allowed)."""
+    cnt = np.concatenate([np.diff(m.lat_offsets) for m in parts])
+    off = np.zeros(len(cnt) + 1, np.int64)
+    np.cumsum(cnt, out=off[1:])
+    return inputs.CsrMesh(np.concatenate([m.p1 for m in parts]),
+                          np.concatenate([m.p2 for m in parts]), parts[0].lat_z, off,
+                          np.concatenate([m.lat_idx for m in parts]))
+
+
+@pytest.mark.parametrize("mode", ["eft", "naive"])
+def test_csr_run_shapes(torch_cuda, mode):
+    """Candidate runs the pair-to-arc table has to tile: runs of several hundred to over a
+    thousand latitudes (longer than the fill's 512-entry window), a stretch of 300 empty arcs,
+    short runs, a last arc with a long run, and an arc count that is no multiple of 64."""
+    g = inputs.rng(109)
+    long_ = inputs.random_mesh(g, 24, 3600, d_hi=1.2)
+    short = inputs.random_mesh(g, 500, 3600, d_hi=0.02)
+    last = inputs.random_mesh(g, 1, 3600, d_hi=1.2)
+    empty = inputs.CsrMesh(short.p1[:300], short.p2[:300], short.lat_z,
+                           np.zeros(301, np.int64), np.zeros(0, np.int32))
+    m = concat_meshes([long_, empty, short, last])
+    runs = np.diff(m.lat_offsets)
+    assert m.n_arcs % 64 and runs.max() > 1024 and np.sum(runs > 512) >= 3 and runs[-1] > 200
+    note(f"csr run shapes {mode}: arcs={m.n_arcs} nnz={m.nnz} longest run={runs.max()}")
+    res = gpu_csr(torch_cuda, m, mode)
+    (check_eft if mode == "eft" else check_naive)(res, m.expand().soa())
+
+
 def test_csr_bad_latitude_index_is_flagged(torch_cuda):
     m = inputs.random_mesh(inputs.rng(108), 200, 50)
     m.lat_idx[::7] = 10_000          # out of range: must become NONFINITE, not an OOB read
