@@ -434,8 +434,10 @@ def main():
 
         def call(out, mode):
             sphint.arc_constlat(tuple(dp[:3]), tuple(dp[3:]), lz, off, idx, mode=mode, out=out)
-        # every input array once (endpoints, offsets, indices, latitudes) + counts and flags
-        bytes_in = 48 * mesh.n_arcs + 8 * (mesh.n_arcs + 1) + 4 * n + 8 * len(mesh.lat_z) + 2 * n
+        # what the main kernel reads and writes once: endpoints, each pair's arc (the
+        # pair-to-arc table the init launch writes from the offsets), latitude indices, the
+        # latitude table, counts and flags (+ hits below)
+        bytes_in = 48 * mesh.n_arcs + 4 * n + 4 * n + 8 * len(mesh.lat_z) + 2 * n
         csr = True
     torch.cuda.synchronize()
 
