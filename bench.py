@@ -548,11 +548,31 @@ def bench_batch(args, torch, np, inputs, sphint):
             plan.launch()
         torch.cuda.synchronize()
         t_batch = (time.perf_counter() - t0) / args.steps
+        # device time of each graph launch (HIP events on the launch stream around it)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for e0, e1 in ev:
+            e0.record()
+            plan.launch()
+            e1.record()
+        torch.cuda.synchronize()
+        dms = [e0.elapsed_time(e1) for e0, e1 in ev]
         plan.check()
         hits = sum(int(d["out"].total.item()) for d in devs)
-        res[mode] = dict(ms_per_step=t_batch * 1e3, per_mesh_ms=t_per * 1e3,
-                         speedup_vs_per_mesh=t_per / t_batch, params=plan.params(),
-                         autotune_s=t_tune, hits=hits, value=nnz / t_batch)
+        hitpairs = sum(int((d["out"].count > 0).sum().item()) for d in devs)
+        # algorithmic bytes of one launch: endpoints and offsets per arc, latitude index,
+        # count and flags per pair, the latitude tables, and the hits; the binding roof (HBM
+        # or binary64 ALU) of the whole graph launch, whose batched kernel dominates it
+        byts = sum(48 * m.n_arcs + 8 * (m.n_arcs + 1) + 6 * m.nnz + 8 * len(m.lat_z)
+                   for m in meshes) + BYTES_PER_HIT * hits
+        kname = (f"graph launch: k_batch<{1 if mode == 'eft' else 0},{plan.params()[0]},true> "
+                 "with its init and pair-to-arc launches")
+        roof = roofline(mode, {"kernel_ms": dms, "total": hits, "hitpairs": hitpairs}, nnz, byts,
+                        kname, None)
+        res[mode] = dict(ms_per_step=t_batch * 1e3, device_ms=statistics.mean(dms),
+                         per_mesh_ms=t_per * 1e3, speedup_vs_per_mesh=t_per / t_batch,
+                         params=plan.params(), autotune_s=t_tune, hits=hits,
+                         value=nnz / t_batch, roofline=roof)
         plan.close()
         log(f"[bench] batch {mode}: {t_batch * 1e3:.2f} ms (per-mesh launches {t_per * 1e3:.2f} ms), "
             f"params {res[mode]['params']}")
@@ -566,6 +586,7 @@ def bench_batch(args, torch, np, inputs, sphint):
         "config": {"workload": "64 meshes, log-uniform 1e3..1e7 arcs (d <= 0.05 rad) x 10..3600 "
                                "latitudes, CSR; one autotuned persistent hipGraph launch, mode " + head,
                    "pairs": nnz, "hits": r["hits"]},
+        "roofline": r["roofline"],
         "batch": res,
     }
     if cpu is not None:
