@@ -109,7 +109,9 @@ typedef struct {
  * workspace   device memory of at least sphint_workspace_size(nnz) bytes, 256-byte
  *             aligned, used only by this call while it runs.
  * Returns SPHINT_E_INVAL (no launch) for negative sizes, missing pointers, mismatched
- * dense sizes, n_arcs >= 2^32 in the CSR form or a short workspace; SPHINT_E_HIP if a launch fails; else SPHINT_OK.
+ * dense sizes, n_arcs >= 2^32 in the CSR form, nnz > 2^40 or more than 2^31 - 1 tiles of
+ * 192 (EFT) or 256 (naive) pairs, or a short workspace; SPHINT_E_HIP if a launch fails;
+ * else SPHINT_OK.
  */
 sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1, sphint_pts_soa p2,
                                   const double *lat_z, int64_t n_lat,

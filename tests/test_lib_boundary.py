@@ -66,6 +66,11 @@ def _call(**kw):
     dict(p1=sphint.PtsSoA(1, None, 3)), dict(out=sphint.Hits(None, 9, 10, 11, 8)),
     dict(off=100, idx=None, nnz=3), dict(off=100, idx=200, nnz=3, n_lat=0),
     dict(out=sphint.Hits(8, 9, 10, 11, -1)),
+    # size limits: more than 2^40 pairs; more than 2^31 tiles of 192 pairs (EFT); 2^32 arcs
+    # in CSR form (arc ids are 32-bit) -- all rejected on the host, with no memory touched
+    dict(n=2**40 + 1, nnz=2**40 + 1, n_lat=2**40 + 1, ws_bytes=1 << 62),
+    dict(n=5 * 10**11, nnz=5 * 10**11, n_lat=5 * 10**11, ws_bytes=1 << 62),
+    dict(off=100, idx=200, n=2**32, nnz=4, ws_bytes=1 << 62),
 ])
 def test_invalid_arguments_rejected_before_launch(bad):
     assert _call(**bad) == sphint.E_INVAL
