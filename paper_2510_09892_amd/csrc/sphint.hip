@@ -64,15 +64,15 @@ constexpr int WG_PER_CU_SINGLE = 4;  // resident workgroups per CU of the persis
 // (queried once).
 template <int MODE, bool CSR>
 int resident_per_cu() {
-  static int cached = 0;
-  if (!cached) {
-    int b = 0;
+  static std::atomic<int> cached{0};  // calls may come from several host threads
+  int b = cached.load(std::memory_order_relaxed);
+  if (!b) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_intersect_w<MODE, wppt_single<MODE>(), CSR>,
                                                      BLOCK, 0) != hipSuccess || b <= 0)
       b = 1;
-    cached = b;
+    cached.store(b, std::memory_order_relaxed);
   }
-  return cached;
+  return b;
 }
 
 template <int MODE, bool CSR>
