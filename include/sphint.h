@@ -68,6 +68,12 @@ typedef enum {
 #define SPHINT_F_DEGEN_N 4u   /* n == 0: zero, equal or antipodal endpoints */
 #define SPHINT_F_HORIZ 8u     /* n_xy == 0, n != 0: the arc lies on the equator */
 #define SPHINT_F_NONFINITE 16u/* an input is inf or nan */
+/* Diagnostic bits (EFT mode only; not part of the result a pair is compared on): */
+#define SPHINT_F_FALLBACK 32u /* a floating-point filter could not certify one of the pair's
+                               * signs, which exact expansion arithmetic then decided */
+#define SPHINT_F_INTERNAL 64u /* an exact evaluation outgrew its fixed buffer (inputs outside
+                               * binary64's normal range); that sign was taken as 0, and
+                               * sphint_check reports SPHINT_E_DEVICE for the call */
 
 #define SPHINT_ROOT_PLUS 0
 #define SPHINT_ROOT_MINUS 1
@@ -305,9 +311,11 @@ sphint_status sphint_circle_points(int64_t n, sphint_pts_soa p1, sphint_pts_soa 
  *                      divisions in plain binary64.
  *   SPHINT_EFT_FP64    n_A and n_B by AccuDOP (Alg. 4) as compensated pairs; the four
  *                      orientation signs exact (two filter stages, then exact expansion
- *                      arithmetic); each component of n_A x n_B by CompDot (Alg. 2) over
- *                      the pairs, |.|^2 by SumOfSquares (Alg. 5), one square root, three
- *                      divisions.  Counts and flags are exact; the point is within a few
+ *                      arithmetic); each component of n_A x n_B by AccuDOP (Alg. 4) on
+ *                      the leading parts of the two pairs plus the four first-order
+ *                      products of their trailing parts (the trailing x trailing products
+ *                      lie below u^2 of the result), |.|^2 by SumOfSquares (Alg. 5), one
+ *                      square root, three divisions.  Counts and flags are exact; the point is within a few
  *                      units of 2^-53 of the exact one (the same input range as above).
  *
  * Pairs: pair k takes arc ia[k] of A (arc k when ia == NULL, then n_a must equal n_pairs)

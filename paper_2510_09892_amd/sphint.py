@@ -20,6 +20,7 @@ MODES = {"naive": NAIVE, "naive_fp64": NAIVE, "eft": EFT, "eft_fp64": EFT, NAIVE
 
 OK, E_INVAL, E_CAPACITY, E_HIP, E_NOMEM, E_DEVICE = range(6)
 F_EXISTS, F_TANGENT, F_DEGEN_N, F_HORIZ, F_NONFINITE = 1, 2, 4, 8, 16
+F_FALLBACK, F_INTERNAL = 32, 64  # diagnostic bits of the EFT mode
 ROOT_PLUS, ROOT_MINUS = 0, 1
 F_RECOMPUTED = 128
 AA_HIT, AA_DEGEN, AA_COPLANAR, AA_NONFINITE, AA_EXACT, AA_INTERNAL = 1, 4, 8, 16, 32, 64
@@ -142,6 +143,67 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _req(t, dtype, name, device=None, length=None):
+    """Raises SphintError unless t is a contiguous CUDA tensor of `dtype` (on `device`, with
+    `length` elements when given): a host tensor, a strided view or a short array must not
+    reach a kernel as a raw pointer."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda:
+        raise SphintError(f"{name} must be a {dtype} CUDA tensor")
+    if not t.is_contiguous():
+        raise SphintError(f"{name} must be contiguous")
+    if device is not None and t.device != device:
+        raise SphintError(f"{name} is on {t.device}, expected {device}")
+    if length is not None and t.numel() != length:
+        raise SphintError(f"{name} has {t.numel()} entries, expected {length}")
+    return t
+
+
+def _check_pairs(p1, p2, lat_z, lat_offsets, lat_idx):
+    """Validates one mesh's tensors; returns (PtsSoA p1, PtsSoA p2, n_arcs, nnz)."""
+    import torch
+    s1, n_arcs = _soa(p1)
+    s2, n2 = _soa(p2)
+    if n2 != n_arcs:
+        raise SphintError("p1 and p2 differ in length")
+    _req(lat_z, torch.float64, "lat_z")
+    dev = lat_z.device
+    for comp in (*(p1 if not isinstance(p1, torch.Tensor) else (p1,)),
+                 *(p2 if not isinstance(p2, torch.Tensor) else (p2,))):
+        if comp.device != dev:
+            raise SphintError("endpoints and lat_z must be on one device")
+    if lat_offsets is None:
+        if lat_idx is not None:
+            raise SphintError("lat_idx given without lat_offsets")
+        if lat_z.numel() != n_arcs:
+            raise SphintError("dense form: lat_z needs one latitude per arc")
+        nnz = n_arcs
+    else:
+        if lat_idx is None:
+            raise SphintError("CSR form needs lat_idx")
+        _req(lat_offsets, torch.int64, "lat_offsets", dev, n_arcs + 1)
+        _req(lat_idx, torch.int32, "lat_idx", dev)
+        nnz = lat_idx.numel()
+    return s1, s2, n_arcs, nnz
+
+
+def _check_output(out, nnz, dev):
+    """The Output must be sized for nnz pairs and live on the inputs' device."""
+    import torch
+    if out.nnz != nnz:
+        raise SphintError("output buffers sized for a different number of pairs")
+    cap = out.capacity
+    for t, dt, name, n in ((out.x, torch.float64, "out.x", cap), (out.y, torch.float64, "out.y", cap),
+                           (out.pair, torch.int64, "out.pair", cap),
+                           (out.root, torch.uint8, "out.root", cap),
+                           (out.count, torch.uint8, "out.count", nnz),
+                           (out.total, torch.int64, "out.total", 1),
+                           (out.workspace, torch.uint8, "out.workspace", out.ws_bytes)):
+        _req(t, dt, name, dev, n)
+    if out.flags is not None:
+        _req(out.flags, torch.uint8, "out.flags", dev, nnz)
+
+
 def _soa(p):
     """(x, y, z) device float64 tensors -> PtsSoA; accepts a (3, n) tensor too."""
     import torch
@@ -150,8 +212,13 @@ def _soa(p):
             raise SphintError("endpoints must be (x, y, z) tensors or a (3, n) tensor")
         p = (p[0], p[1], p[2])
     for t in p:
-        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda
+                or not t.is_contiguous()):
             raise SphintError("endpoint components must be contiguous float64 CUDA tensors")
+    if not (p[0].numel() == p[1].numel() == p[2].numel()) or p[0].dim() != 1:
+        raise SphintError("endpoint components must be 1-D and of equal length")
+    if not (p[0].device == p[1].device == p[2].device):
+        raise SphintError("endpoint components must be on one device")
     return PtsSoA(p[0].data_ptr(), p[1].data_ptr(), p[2].data_ptr()), len(p[0])
 
 
@@ -201,24 +268,11 @@ def arc_constlat(p1, p2, lat_z, lat_offsets=None, lat_idx=None, mode="eft", out=
     Dense form: lat_z has one latitude per arc.  CSR form: lat_offsets (int64, n_arcs + 1)
     and lat_idx (int32, nnz) index into lat_z.  Nothing is synchronised.
     """
-    import torch
     lib = load()
-    s1, n_arcs = _soa(p1)
-    s2, n2 = _soa(p2)
-    if n2 != n_arcs:
-        raise SphintError("p1 and p2 differ in length")
-    if lat_z.dtype != torch.float64 or not lat_z.is_cuda:
-        raise SphintError("lat_z must be a float64 CUDA tensor")
-    if lat_offsets is None:
-        nnz = n_arcs
-    else:
-        if lat_offsets.dtype != torch.int64 or lat_idx is None or lat_idx.dtype != torch.int32:
-            raise SphintError("CSR form needs int64 lat_offsets and int32 lat_idx")
-        nnz = len(lat_idx)
+    s1, s2, n_arcs, nnz = _check_pairs(p1, p2, lat_z, lat_offsets, lat_idx)
     if out is None:
         out = Output(nnz, device=lat_z.device)
-    if out.nnz != nnz:
-        raise SphintError("output buffers sized for a different number of pairs")
+    _check_output(out, nnz, lat_z.device)
     st = lib.sphint_arc_constlat(n_arcs, s1, s2, _ptr(lat_z), len(lat_z), _ptr(lat_offsets),
                                  _ptr(lat_idx), nnz, out.hits_struct(), _ptr(out.count),
                                  _ptr(out.flags), _ptr(out.total), MODES[mode],
@@ -444,10 +498,11 @@ class BatchPlan:
         self._keep = meshes
         arr = (MeshDesc * len(meshes))()
         for k, m in enumerate(meshes):
-            s1, n_arcs = _soa(m["p1"])
-            s2, _ = _soa(m["p2"])
-            out = m["out"]
             off = m.get("lat_offsets")
+            s1, s2, n_arcs, nnz = _check_pairs(m["p1"], m["p2"], m["lat_z"], off,
+                                               m.get("lat_idx"))
+            out = m["out"]
+            _check_output(out, nnz, m["lat_z"].device)
             arr[k] = MeshDesc(n_arcs, len(m["lat_z"]), out.nnz, s1, s2, m["lat_z"].data_ptr(),
                               off.data_ptr() if off is not None else None,
                               m["lat_idx"].data_ptr() if off is not None else None,

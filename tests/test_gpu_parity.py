@@ -242,3 +242,46 @@ def test_csr_bad_latitude_index_is_flagged(torch_cuda):
     bad = np.zeros(m.nnz, bool)
     bad[::7] = True
     assert np.all(res["flags"][bad] == 16) and np.all(res["count"][bad] == 0)
+
+
+def test_binding_rejects_malformed_tensors_before_launch(torch_cuda):
+    """Short, strided, host or mistyped CSR/output tensors raise before any kernel runs."""
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    m = inputs.random_mesh(inputs.rng(77), 300, 40)
+    p = to_dev(torch, [m.p1[:, 0], m.p1[:, 1], m.p1[:, 2], m.p2[:, 0], m.p2[:, 1], m.p2[:, 2]])
+    lz = torch.from_numpy(m.lat_z).cuda()
+    off = torch.from_numpy(m.lat_offsets).cuda()
+    idx = torch.from_numpy(m.lat_idx).cuda()
+    p1, p2 = tuple(p[:3]), tuple(p[3:])
+    good = sphint.arc_constlat(p1, p2, lz, off, idx, mode="eft")
+    torch.cuda.synchronize()
+    good.check()
+    bad_cases = {
+        "short offsets": dict(lat_offsets=off[:-1]),
+        "host offsets": dict(lat_offsets=off.cpu()),
+        "strided idx": dict(lat_idx=torch.stack([idx, idx], 1)[:, 0]),
+        "int64 idx": dict(lat_idx=idx.long()),
+        "host lat_z": dict(lat_z=lz.cpu()),
+        "idx without offsets": dict(lat_offsets=None),
+    }
+    for name, kw in bad_cases.items():
+        args = dict(lat_z=lz, lat_offsets=off, lat_idx=idx)
+        args.update(kw)
+        with pytest.raises(sphint.SphintError):
+            sphint.arc_constlat(p1, p2, args["lat_z"], args["lat_offsets"], args["lat_idx"])
+        note(f"rejected: {name}")
+    wrong = sphint.Output(len(idx) + 1)
+    with pytest.raises(sphint.SphintError):
+        sphint.arc_constlat(p1, p2, lz, off, idx, out=wrong)
+    out = sphint.Output(len(idx))
+    out.count = out.count[:-1]
+    with pytest.raises(sphint.SphintError):
+        sphint.arc_constlat(p1, p2, lz, off, idx, out=out)
+    with pytest.raises(sphint.SphintError):  # dense form with a latitude array of another size
+        sphint.arc_constlat(p1, p2, lz[:10])
+    # the same mesh in a batch plan: a short offsets tensor is refused at plan creation
+    mesh = dict(p1=p1, p2=p2, lat_z=lz, lat_offsets=off[:-1], lat_idx=idx,
+                out=sphint.Output(len(idx)))
+    with pytest.raises(sphint.SphintError):
+        sphint.BatchPlan([mesh])

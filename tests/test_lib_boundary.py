@@ -149,3 +149,50 @@ def test_circle_points_invalid_arguments():
                 dict(p1=P(1, None, 3))):
         assert call(**bad) == sphint.E_INVAL, bad
     assert call(n=0, z0=None, x=None, y=None, o=None) == sphint.OK
+
+
+def _defines(text, prefix):
+    return {m.group(1): int(m.group(2)) for m in
+            re.finditer(r"#define\s+(" + prefix + r"[A-Z0-9_]+)\s+(\d+)u?", text)}
+
+
+def _enum_values(path, names):
+    text = open(path).read()
+    return {n: int(re.search(r"\b" + n + r"\s*=\s*(\d+)u?", text).group(1)) for n in names}
+
+
+def test_flag_bits_agree_across_header_kernels_and_binding():
+    """The bits the kernels write are the ones the header and the binding name."""
+    hdr = open(HEADER).read()
+    csrc = os.path.join(ROOT, "paper_2510_09892_amd", "csrc")
+    f = _defines(hdr, "SPHINT_F_")
+    k = _enum_values(os.path.join(csrc, "sphint_pair.hpp"),
+                     ["F_EXISTS", "F_TANGENT", "F_DEGEN_N", "F_HORIZ", "F_NONFINITE",
+                      "F_FALLBACK", "F_INTERNAL"])
+    for name, v in k.items():
+        assert f["SPHINT_" + name] == v, name
+        assert getattr(sphint, name) == v, name
+    assert f["SPHINT_F_RECOMPUTED"] == sphint.F_RECOMPUTED  # the adaptive kernel uses the macro
+    # the kernels' internal re-evaluation marker never reaches out_flags as a public bit
+    internal = _enum_values(os.path.join(csrc, "sphint_pair.hpp"), ["F_NEEDEXACT"])
+    assert internal["F_NEEDEXACT"] not in {v for n, v in f.items() if n != "SPHINT_F_RECOMPUTED"}
+    aa = _defines(hdr, "SPHINT_AA_")
+    ka = _enum_values(os.path.join(csrc, "sphint_arcarc.hpp"),
+                      ["AA_HIT", "AA_DEGEN", "AA_COPLANAR", "AA_NONFINITE", "AA_EXACT",
+                       "AA_INTERNAL"])
+    for name, v in ka.items():
+        assert aa["SPHINT_" + name] == v, name
+        assert getattr(sphint, name) == v, name
+
+
+def test_binding_rejects_host_tensors_before_any_call():
+    """Host tensors never reach the library as device pointers (no GPU needed)."""
+    import torch
+    z = torch.zeros(4, dtype=torch.float64)
+    p = (z, z, z)
+    with pytest.raises(sphint.SphintError):
+        sphint.arc_constlat(p, p, z)
+    with pytest.raises(sphint.SphintError):
+        sphint._req(z, torch.float64, "lat_z")
+    with pytest.raises(sphint.SphintError):
+        sphint._soa((z, z))
