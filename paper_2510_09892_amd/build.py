@@ -70,5 +70,32 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_hostcheck_sanitized(out: str, verbose: bool = False) -> str:
+    """The CPU test build under AddressSanitizer and UndefinedBehaviorSanitizer (host code
+    only; no GPU code is involved).  Load it with the sanitizer runtime preloaded:
+
+        LD_PRELOAD=$(python -m paper_2510_09892_amd.build --asan-runtime) \
+        ASAN_OPTIONS=detect_leaks=0 SPHINT_HOSTCHECK_LIB=<out> python -m pytest tests/...
+    """
+    _run([_clang(), "-x", "hip", "--cuda-host-only", *COMMON, "-O1", "-g",
+          "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address,undefined",
+          "-Xarch_host", "-fno-sanitize-recover=undefined", "-shared-libsan",
+          os.path.join(CSRC, "sphint_hostcheck.cpp"), "-o", out], verbose)
+    return out
+
+
+def asan_runtime() -> str:
+    """Path of clang's shared AddressSanitizer runtime (for LD_PRELOAD)."""
+    r = subprocess.run([_clang(), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True, check=True)
+    return r.stdout.strip()
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--asan-runtime" in sys.argv:
+        print(asan_runtime())
+    elif "--sanitized" in sys.argv:
+        print(build_hostcheck_sanitized(sys.argv[sys.argv.index("--sanitized") + 1],
+                                        verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

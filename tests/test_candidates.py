@@ -20,8 +20,10 @@ import pytest
 from oracle import batch as OB, geometry as G
 from paper_2510_09892_amd import inputs
 
-LIBPATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                       "paper_2510_09892_amd", "libsphint_hostcheck.so")
+# SPHINT_HOSTCHECK_LIB selects another build of the same sources (e.g. the sanitizer build)
+LIBPATH = os.environ.get("SPHINT_HOSTCHECK_LIB") or os.path.join(
+    os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2510_09892_amd",
+    "libsphint_hostcheck.so")
 SLACK = 2.0 ** -46
 
 

@@ -24,8 +24,10 @@ from oracle import batch as OB, geometry as G, naive as ON
 from paper_2510_09892_amd import inputs
 
 U = 2.0 ** -53
-LIBPATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                       "paper_2510_09892_amd", "libsphint_hostcheck.so")
+# SPHINT_HOSTCHECK_LIB selects another build of the same sources (e.g. the sanitizer build)
+LIBPATH = os.environ.get("SPHINT_HOSTCHECK_LIB") or os.path.join(
+    os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2510_09892_amd",
+    "libsphint_hostcheck.so")
 FLAG_MASK = 31  # EXISTS | TANGENT | DEGEN_N | HORIZ | NONFINITE (diagnostic bits excluded)
 
 

@@ -23,8 +23,10 @@ from oracle.geometry import scaled_ints
 from paper_2510_09892_amd import inputs
 
 U = 2.0 ** -53
-LIBPATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                       "paper_2510_09892_amd", "libsphint_hostcheck.so")
+# SPHINT_HOSTCHECK_LIB selects another build of the same sources (e.g. the sanitizer build)
+LIBPATH = os.environ.get("SPHINT_HOSTCHECK_LIB") or os.path.join(
+    os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2510_09892_amd",
+    "libsphint_hostcheck.so")
 MASK = AA.HIT | AA.DEGEN | AA.COPLANAR | AA.NONFINITE
 EXACT = 32
 
