@@ -255,10 +255,13 @@ def cubed_sphere_edges(ne: int):
         lat[..., free[0]] = I
         lat[..., free[1]] = J
         keys.append(lat.reshape(-1, 3))
-    lattice = np.unique(np.concatenate(keys), axis=0)
-    code = lattice[:, 0] * (ne + 1) ** 2 + lattice[:, 1] * (ne + 1) + lattice[:, 2]
-    order = np.argsort(code)
-    code_sorted = code[order]
+    # unique lattice points in lexicographic order (a scalar key sorts the same way, since
+    # every coordinate lies in [0, ne])
+    allkeys = np.concatenate(keys)
+    code_sorted = np.unique(allkeys[:, 0] * (ne + 1) ** 2 + allkeys[:, 1] * (ne + 1) + allkeys[:, 2])
+    lattice = np.stack([code_sorted // (ne + 1) ** 2, (code_sorted // (ne + 1)) % (ne + 1),
+                        code_sorted % (ne + 1)], axis=1)
+    order = np.arange(len(code_sorted))
     xyz = t[lattice]
     pts = xyz / np.linalg.norm(xyz, axis=1, keepdims=True)
     edges = []
@@ -278,8 +281,10 @@ def cubed_sphere_edges(ne: int):
             ia = order[np.searchsorted(code_sorted, ca)]
             ib = order[np.searchsorted(code_sorted, cb)]
             edges.append(np.stack([np.minimum(ia, ib), np.maximum(ia, ib)], axis=1))
-    e = np.unique(np.concatenate(edges), axis=0)
-    return pts[e[:, 0]], pts[e[:, 1]]
+    e = np.concatenate(edges)
+    npts = np.int64(len(pts))
+    ekey = np.unique(e[:, 0] * npts + e[:, 1])  # lexicographic (low node, high node) order
+    return pts[ekey // npts], pts[ekey % npts]
 
 
 def cubed_sphere(ne: int = 1024, n_lat: int = 1800, first_deg: float = -89.95,
