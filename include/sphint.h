@@ -140,6 +140,36 @@ size_t sphint_workspace_size(int64_t nnz);
 sphint_status sphint_check(const void *workspace, int64_t host_total, int64_t capacity);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): sphint_arc_constlat without a
+ * workspace argument.  The same kernels run with the same results; their workspace (the
+ * error word, the tile scan states and, for the CSR form, the pair-to-arc table) is a
+ * static device array of SPHINT_NOALLOC_SCRATCH_BYTES inside the library, one per device,
+ * held until the process ends.  Nothing is allocated on any call.
+ *
+ * Scratch a call takes: dense form 256 + 8 * max(1, ceil(nnz / 64)) bytes (up to about
+ * 5.4e8 pairs), CSR form 256 + 8 * max(1, ceil(nnz / 64)) + 4 * nnz bytes (up to about
+ * 1.6e7 pairs); a call that would need more returns SPHINT_E_INVAL before any launch.
+ *
+ * out_error  one int32 (device, may be NULL): after the call, 0, or the kernels' error bits
+ *            (nonzero where sphint_check would report SPHINT_E_DEVICE).  Capacity overflow
+ *            shows as *out_total > out.capacity, as for sphint_arc_constlat.
+ * All calls on one device share that device's array, and each call starts by clearing what
+ * it reads before writing it.  The library orders its own launches on a device across
+ * streams, so calls made directly from one process do not overlap; calls recorded into
+ * graphs (not ordered by the library) that run at the same time on one device race on the
+ * array and give undefined results.  Other arguments and errors as sphint_arc_constlat.
+ */
+#define SPHINT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+sphint_status sphint_arc_constlat_noalloc(int64_t n_arcs, sphint_pts_soa p1, sphint_pts_soa p2,
+                                          const double *lat_z, int64_t n_lat,
+                                          const int64_t *lat_offsets, const int32_t *lat_idx,
+                                          int64_t nnz, sphint_hits out, uint8_t *out_count,
+                                          uint8_t *out_flags, int64_t *out_total,
+                                          int32_t *out_error, sphint_mode mode, void *stream);
+
+/*
  * Instrumentation.  While set (non-NULL), every sphint_arc_constlat call made from this host
  * thread records `start` (a hipEvent_t) on its stream immediately before its main kernel and
  * `stop` immediately after it, so the caller can time that kernel alone, and every

@@ -6,6 +6,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "sphint.h"
 #include "sphint_host.hpp"
 
@@ -32,6 +35,11 @@ __global__ __launch_bounds__(INIT_BLOCK) void k_init(uint32_t* ws, uint64_t* sta
   if (off && nnz > 0)
     fill_pair_arcs(off, n_arcs, nnz, parc, (int64_t)blockIdx.x * (INIT_BLOCK / 64) + wave,
                    (int64_t)gridDim.x * (INIT_BLOCK / 64), win[wave]);
+}
+
+// Copies a call's error bits (the workspace header's error word) to a caller's device word.
+__global__ __launch_bounds__(64) void k_error_out(const uint32_t* ws, int32_t* out_error) {
+  if (threadIdx.x == 0) *out_error = (int32_t)ws[1];
 }
 
 }  // namespace
@@ -92,6 +100,58 @@ hipError_t launch_main(const KArgs& k, hipStream_t st) {
 
 extern "C" size_t sphint_workspace_size(int64_t nnz) { return workspace_bytes_for(nnz); }
 
+// The body of sphint_arc_constlat and sphint_arc_constlat_noalloc: arguments validated,
+// `ws_base` points at workspace_bytes_for(nnz) (dense calls: the header and tile states
+// only) bytes of device memory, 256-byte aligned.
+static sphint_status arc_constlat_on(int64_t n_arcs, const sphint_pts_soa& p1,
+                                     const sphint_pts_soa& p2, const double* lat_z,
+                                     int64_t n_lat, const int64_t* lat_offsets,
+                                     const int32_t* lat_idx, int64_t nnz, const sphint_hits& out,
+                                     uint8_t* out_count, uint8_t* out_flags, int64_t* out_total,
+                                     sphint_mode mode, void* ws_base, int64_t ntiles,
+                                     hipStream_t st, int32_t* out_error) {
+  uint32_t* ws = (uint32_t*)ws_base;
+  uint64_t* status = (uint64_t*)((char*)ws_base + WS_HEADER);
+
+  LaunchChain chain;
+  if (chain.begin(st) != hipSuccess) return SPHINT_E_HIP;
+  uint32_t* parc = (uint32_t*)((char*)ws_base + WS_HEADER + 8 * status_words_for(nnz));
+  int64_t init_blocks = (ntiles + INIT_BLOCK - 1) / INIT_BLOCK;  // one lane per tile state
+  if (init_blocks > 8192) init_blocks = 8192;
+  if (lat_offsets && nnz > 0 && fill_blocks(n_arcs) > init_blocks)
+    init_blocks = fill_blocks(n_arcs);
+  if (init_blocks < 1) init_blocks = 1;
+  hipLaunchKernelGGL(k_init, dim3((unsigned)init_blocks), dim3(INIT_BLOCK), 0, st, ws, status,
+                     ntiles, out_total, nnz, lat_offsets, n_arcs, parc);
+  if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
+  hipError_t e = hipSuccess;
+  if (nnz > 0) {
+    KArgs k = make_args(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out, out_count,
+                        out_flags, out_total, ws, status, ntiles, parc);
+    if (profile_events().start && hipEventRecord(profile_events().start, st) != hipSuccess)
+      return SPHINT_E_HIP;
+    const bool csr = lat_offsets != nullptr;
+    if (mode == SPHINT_EFT_FP64)
+      e = csr ? launch_main<1, true>(k, st) : launch_main<1, false>(k, st);
+    else
+      e = csr ? launch_main<0, true>(k, st) : launch_main<0, false>(k, st);
+    if (e == hipSuccess && profile_events().stop) e = hipEventRecord(profile_events().stop, st);
+  }
+  if (e == hipSuccess && out_error) {
+    hipLaunchKernelGGL(k_error_out, dim3(1), dim3(64), 0, st, (const uint32_t*)ws, out_error);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = chain.end();
+  return e == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
+}
+
+// Number of tiles of one call, or -1 when there would be too many for the launch.
+static int64_t call_tiles(int64_t nnz, sphint_mode mode) {
+  const int64_t ntiles =
+      wave_tiles_for(nnz, mode == SPHINT_EFT_FP64 ? wppt_single<1>() : wppt_single<0>());
+  return ntiles > 0x7fffffffLL ? -1 : ntiles;
+}
+
 extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
                                              sphint_pts_soa p2, const double* lat_z,
                                              int64_t n_lat, const int64_t* lat_offsets,
@@ -106,37 +166,69 @@ extern "C" sphint_status sphint_arc_constlat(int64_t n_arcs, sphint_pts_soa p1,
   if (v != SPHINT_OK) return v;
   if (!workspace || !aligned256(workspace) || workspace_bytes < sphint_workspace_size(nnz))
     return SPHINT_E_INVAL;
-  const int64_t ntiles =
-      wave_tiles_for(nnz, mode == SPHINT_EFT_FP64 ? wppt_single<1>() : wppt_single<0>());
-  if (ntiles > 0x7fffffffLL) return SPHINT_E_INVAL;
-  hipStream_t st = (hipStream_t)stream;
-  uint32_t* ws = (uint32_t*)workspace;
-  uint64_t* status = (uint64_t*)((char*)workspace + WS_HEADER);
+  const int64_t ntiles = call_tiles(nnz, mode);
+  if (ntiles < 0) return SPHINT_E_INVAL;
+  return arc_constlat_on(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out,
+                         out_count, out_flags, out_total, mode, workspace, ntiles,
+                         (hipStream_t)stream, nullptr);
+}
 
-  LaunchChain chain;
-  if (chain.begin(st) != hipSuccess) return SPHINT_E_HIP;
-  uint32_t* parc = (uint32_t*)((char*)workspace + WS_HEADER + 8 * status_words_for(nnz));
-  int64_t init_blocks = (ntiles + INIT_BLOCK - 1) / INIT_BLOCK;  // one lane per tile state
-  if (init_blocks > 8192) init_blocks = 8192;
-  if (lat_offsets && nnz > 0 && fill_blocks(n_arcs) > init_blocks)
-    init_blocks = fill_blocks(n_arcs);
-  if (init_blocks < 1) init_blocks = 1;
-  hipLaunchKernelGGL(k_init, dim3((unsigned)init_blocks), dim3(INIT_BLOCK), 0, st, ws, status,
-                     ntiles, out_total, nnz, lat_offsets, n_arcs, parc);
-  if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
-  if (nnz == 0) return chain.end() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
+// ------------------------------------------------------------ allocation-free variant
+//
+// The workspace of sphint_arc_constlat_noalloc lives in this array: one copy per device
+// (each device that runs the library holds it until the process ends).  Host code never
+// uses the array's name as a device address: its address on each device comes from
+// hipGetSymbolAddress, taken once per device (with that device current) and kept.
+static __device__ __align__(256) unsigned char scratch[SPHINT_NOALLOC_SCRATCH_BYTES];
 
-  KArgs k = make_args(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out, out_count,
-                      out_flags, out_total, ws, status, ntiles, parc);
-  if (profile_events().start && hipEventRecord(profile_events().start, st) != hipSuccess)
-    return SPHINT_E_HIP;
-  const bool csr = lat_offsets != nullptr;
-  hipError_t e;
-  if (mode == SPHINT_EFT_FP64) e = csr ? launch_main<1, true>(k, st) : launch_main<1, false>(k, st);
-  else e = csr ? launch_main<0, true>(k, st) : launch_main<0, false>(k, st);
-  if (e == hipSuccess && profile_events().stop) e = hipEventRecord(profile_events().stop, st);
-  if (e == hipSuccess) e = chain.end();
-  return e == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
+constexpr int MAX_DEVICES = 64;
+
+// Device address of `scratch` on the current device, or nullptr if it cannot be had.
+static void* scratch_on_current_device() {
+  static std::atomic<void*> ptrs[MAX_DEVICES];
+  static std::mutex m;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  void* p = ptrs[dev].load(std::memory_order_acquire);
+  if (p) return p;
+  std::lock_guard<std::mutex> g(m);
+  p = ptrs[dev].load(std::memory_order_relaxed);
+  if (!p) {
+    void* q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return nullptr;
+    ptrs[dev].store(q, std::memory_order_release);
+    p = q;
+  }
+  return p;
+}
+
+// Scratch bytes a call over nnz pairs takes: the header and the tile states, and for the
+// CSR form the pair-to-arc table.
+static size_t noalloc_bytes(int64_t nnz, bool csr) {
+  return csr ? workspace_bytes_for(nnz) : WS_HEADER + 8 * status_words_for(nnz);
+}
+
+extern "C" sphint_status sphint_arc_constlat_noalloc(int64_t n_arcs, sphint_pts_soa p1,
+                                                     sphint_pts_soa p2, const double* lat_z,
+                                                     int64_t n_lat, const int64_t* lat_offsets,
+                                                     const int32_t* lat_idx, int64_t nnz,
+                                                     sphint_hits out, uint8_t* out_count,
+                                                     uint8_t* out_flags, int64_t* out_total,
+                                                     int32_t* out_error, sphint_mode mode,
+                                                     void* stream) {
+  if (mode != SPHINT_NAIVE_FP64 && mode != SPHINT_EFT_FP64) return SPHINT_E_INVAL;
+  sphint_status v = validate(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out,
+                             out_count, out_total);
+  if (v != SPHINT_OK) return v;
+  if (noalloc_bytes(nnz, lat_offsets != nullptr) > SPHINT_NOALLOC_SCRATCH_BYTES)
+    return SPHINT_E_INVAL;
+  const int64_t ntiles = call_tiles(nnz, mode);
+  if (ntiles < 0) return SPHINT_E_INVAL;
+  void* ws = scratch_on_current_device();
+  if (!ws) return SPHINT_E_HIP;
+  return arc_constlat_on(n_arcs, p1, p2, lat_z, n_lat, lat_offsets, lat_idx, nnz, out,
+                         out_count, out_flags, out_total, mode, ws, ntiles, (hipStream_t)stream,
+                         out_error);
 }
 
 extern "C" sphint_status sphint_set_profile_events(void* start, void* stop) {

@@ -23,9 +23,11 @@ F_EXISTS, F_TANGENT, F_DEGEN_N, F_HORIZ, F_NONFINITE = 1, 2, 4, 8, 16
 F_FALLBACK, F_INTERNAL = 32, 64  # diagnostic bits of the EFT mode
 ROOT_PLUS, ROOT_MINUS = 0, 1
 F_RECOMPUTED = 128
+NOALLOC_SCRATCH_BYTES = 64 << 20  # SPHINT_NOALLOC_SCRATCH_BYTES
 AA_HIT, AA_DEGEN, AA_COPLANAR, AA_NONFINITE, AA_EXACT, AA_INTERNAL = 1, 4, 8, 16, 32, 64
 
 EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
+           "sphint_arc_constlat_noalloc",
            "sphint_set_profile_events",
            "sphint_batch_plan_create", "sphint_batch_autotune", "sphint_batch_launch",
            "sphint_batch_params", "sphint_batch_set_params", "sphint_batch_check",
@@ -80,6 +82,9 @@ def load():
     lib.sphint_arc_constlat.argtypes = [i64, PtsSoA, PtsSoA, vp, i64, vp, vp, i64, Hits, vp, vp,
                                         vp, ctypes.c_int, vp, sz, vp]
     lib.sphint_arc_constlat.restype = ctypes.c_int
+    lib.sphint_arc_constlat_noalloc.argtypes = [i64, PtsSoA, PtsSoA, vp, i64, vp, vp, i64, Hits,
+                                                vp, vp, vp, vp, ctypes.c_int, vp]
+    lib.sphint_arc_constlat_noalloc.restype = ctypes.c_int
     lib.sphint_workspace_size.argtypes = [i64]
     lib.sphint_workspace_size.restype = sz
     lib.sphint_set_profile_events.argtypes = [vp, vp]
@@ -197,9 +202,10 @@ def _check_output(out, nnz, dev):
                            (out.pair, torch.int64, "out.pair", cap),
                            (out.root, torch.uint8, "out.root", cap),
                            (out.count, torch.uint8, "out.count", nnz),
-                           (out.total, torch.int64, "out.total", 1),
-                           (out.workspace, torch.uint8, "out.workspace", out.ws_bytes)):
+                           (out.total, torch.int64, "out.total", 1)):
         _req(t, dt, name, dev, n)
+    if out.workspace is not None:
+        _req(out.workspace, torch.uint8, "out.workspace", dev, out.ws_bytes)
     if out.flags is not None:
         _req(out.flags, torch.uint8, "out.flags", dev, nnz)
 
@@ -225,7 +231,9 @@ def _soa(p):
 class Output:
     """Caller-owned device buffers for one call (reusable across calls of the same size)."""
 
-    def __init__(self, nnz, capacity=None, flags=True, device="cuda"):
+    def __init__(self, nnz, capacity=None, flags=True, device="cuda", workspace=True):
+        """workspace=False: no workspace (for arc_constlat_noalloc, whose workspace is the
+        library's own static device array)."""
         import torch
         cap = 2 * nnz if capacity is None else int(capacity)
         self.nnz = nnz
@@ -237,10 +245,14 @@ class Output:
         self.count = torch.empty(nnz, dtype=torch.uint8, device=device)
         self.flags = torch.empty(nnz, dtype=torch.uint8, device=device) if flags else None
         self.total = torch.zeros(1, dtype=torch.int64, device=device)
-        ws = int(load().sphint_workspace_size(nnz))
-        # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
-        self.workspace = torch.empty(ws, dtype=torch.uint8, device=device)
-        self.ws_bytes = ws
+        self.error = torch.zeros(1, dtype=torch.int32, device=device)
+        if workspace:
+            ws = int(load().sphint_workspace_size(nnz))
+            # 256-byte alignment: torch's caching allocator returns 512-byte aligned blocks
+            self.workspace = torch.empty(ws, dtype=torch.uint8, device=device)
+            self.ws_bytes = ws
+        else:
+            self.workspace, self.ws_bytes = None, 0
 
     def hits(self):
         """Synchronises; returns (x, y, pair, root) trimmed to the total."""
@@ -252,6 +264,12 @@ class Output:
     def check(self):
         """Synchronises; raises if the kernel reported an internal limit or overflowed."""
         t = int(self.total.item())
+        if self.workspace is None:  # filled by arc_constlat_noalloc: its error word
+            if int(self.error.item()) != 0:
+                _check(E_DEVICE, "sphint_arc_constlat_noalloc")
+            if t > self.capacity:
+                _check(E_CAPACITY, "sphint_arc_constlat_noalloc")
+            return t
         _check(load().sphint_check(ctypes.c_void_p(self.workspace.data_ptr()), t, self.capacity),
                "sphint_check")
         return t
@@ -273,11 +291,34 @@ def arc_constlat(p1, p2, lat_z, lat_offsets=None, lat_idx=None, mode="eft", out=
     if out is None:
         out = Output(nnz, device=lat_z.device)
     _check_output(out, nnz, lat_z.device)
+    if out.workspace is None:
+        raise SphintError("arc_constlat needs an Output with a workspace")
     st = lib.sphint_arc_constlat(n_arcs, s1, s2, _ptr(lat_z), len(lat_z), _ptr(lat_offsets),
                                  _ptr(lat_idx), nnz, out.hits_struct(), _ptr(out.count),
                                  _ptr(out.flags), _ptr(out.total), MODES[mode],
                                  _ptr(out.workspace), out.ws_bytes, _stream(stream))
     _check(st, "sphint_arc_constlat")
+    return out
+
+
+def arc_constlat_noalloc(p1, p2, lat_z, lat_offsets=None, lat_idx=None, mode="eft", out=None,
+                         stream=None):
+    """Enqueue sphint_arc_constlat_noalloc (no workspace: the library's static device array
+    serves as one); arguments and results as arc_constlat.  The Output's `error` word
+    receives the kernels' error bits."""
+    import torch
+    lib = load()
+    s1, s2, n_arcs, nnz = _check_pairs(p1, p2, lat_z, lat_offsets, lat_idx)
+    if out is None:
+        out = Output(nnz, device=lat_z.device, workspace=False)
+    _check_output(out, nnz, lat_z.device)
+    _req(out.error, torch.int32, "out.error", lat_z.device, 1)
+    st = lib.sphint_arc_constlat_noalloc(n_arcs, s1, s2, _ptr(lat_z), len(lat_z),
+                                         _ptr(lat_offsets), _ptr(lat_idx), nnz,
+                                         out.hits_struct(), _ptr(out.count), _ptr(out.flags),
+                                         _ptr(out.total), _ptr(out.error), MODES[mode],
+                                         _stream(stream))
+    _check(st, "sphint_arc_constlat_noalloc")
     return out
 
 

@@ -76,6 +76,50 @@ def test_invalid_arguments_rejected_before_launch(bad):
     assert _call(**bad) == sphint.E_INVAL
 
 
+def _noalloc(**kw):
+    lib = sphint.load()
+    d = dict(n=4, p1=sphint.PtsSoA(1, 2, 3), p2=sphint.PtsSoA(4, 5, 6), lat_z=7, n_lat=4,
+             off=None, idx=None, nnz=4, out=sphint.Hits(8, 9, 10, 11, 8), count=12, flags=None,
+             total=13, err=None, mode=1, stream=None)
+    d.update(kw)
+    return lib.sphint_arc_constlat_noalloc(d["n"], d["p1"], d["p2"], d["lat_z"], d["n_lat"],
+                                           d["off"], d["idx"], d["nnz"], d["out"], d["count"],
+                                           d["flags"], d["total"], d["err"], d["mode"],
+                                           d["stream"])
+
+
+def _noalloc_limits():
+    """Largest dense and CSR pair counts whose scratch fits SPHINT_NOALLOC_SCRATCH_BYTES."""
+    m = re.search(r"#define\s+SPHINT_NOALLOC_SCRATCH_BYTES\s+\(\(size_t\)(\d+)\s*<<\s*(\d+)\)",
+                  open(HEADER).read())
+    cap = int(m.group(1)) << int(m.group(2))
+    assert cap == sphint.NOALLOC_SCRATCH_BYTES
+    tiles = lambda n: max(1, -(-n // 64))  # noqa: E731
+    dense = (cap - 256) // 8 * 64
+    assert 256 + 8 * tiles(dense) <= cap < 256 + 8 * tiles(dense + 1)
+    csr = (cap - 256 - 8) // 4
+    while 256 + 8 * tiles(csr) + 4 * csr > cap:
+        csr -= 1
+    return dense, csr
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=-1), dict(nnz=5), dict(mode=7), dict(total=None), dict(count=None),
+    dict(p1=sphint.PtsSoA(1, None, 3)), dict(off=100, idx=None, nnz=3),
+    dict(out=sphint.Hits(8, 9, 10, 11, -1)),
+    "dense+1", "csr+1",
+])
+def test_noalloc_rejects_before_launch(bad):
+    """Invalid arguments, and any call whose scratch would exceed the static array, are
+    rejected on the host before the array or the device is touched."""
+    dense, csr = _noalloc_limits()
+    if bad == "dense+1":
+        bad = dict(n=dense + 1, nnz=dense + 1, n_lat=dense + 1)
+    elif bad == "csr+1":
+        bad = dict(off=100, idx=200, n=1000, nnz=csr + 1)
+    assert _noalloc(**bad) == sphint.E_INVAL
+
+
 def test_batch_rejects_bad_arguments():
     lib = sphint.load()
     h = ctypes.c_void_p()
