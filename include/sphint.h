@@ -226,6 +226,31 @@ sphint_status sphint_batch_set_params(sphint_plan *plan, int pairs_per_thread, i
 sphint_status sphint_batch_check(const sphint_plan *plan);
 void sphint_plan_destroy(sphint_plan *plan);
 
+/*
+ * One-shot batched launch, for continuous batching (a request loop whose set of meshes
+ * changes on every launch): up to SPHINT_BATCH_RUN_MAX meshes of one form (all CSR or all
+ * dense) in one persistent launch, without a plan.  The meshes' arguments travel to the
+ * device with the launch (as kernel arguments), so the call allocates nothing and does not
+ * synchronise: an init kernel writes them into `workspace`, clears the tile states and
+ * fills the CSR pair-to-arc tables, and the plan's persistent batched kernel follows on
+ * `stream` (pairs per lane as in sphint_arc_constlat).  Each mesh's outputs equal a
+ * sphint_arc_constlat call on that mesh alone.
+ *
+ * workspace   device memory of at least sphint_batch_run_workspace_size(n_meshes, sum of
+ *             the meshes' nnz) bytes, 256-byte aligned, used only by this launch while it
+ *             runs (a later launch on the same stream may reuse it).  After the stream has
+ *             completed the launch, sphint_check(workspace, total, capacity) reports the
+ *             kernels' error word for every mesh of the launch.
+ * SPHINT_E_INVAL (no launch) for n_meshes outside [1, SPHINT_BATCH_RUN_MAX], mixed forms, a
+ * mesh that sphint_arc_constlat would reject, more than 2^40 pairs in all or a short or
+ * misaligned workspace; SPHINT_E_HIP if a launch fails.
+ */
+#define SPHINT_BATCH_RUN_MAX 16
+
+size_t sphint_batch_run_workspace_size(int n_meshes, int64_t total_nnz);
+sphint_status sphint_batch_run(const sphint_mesh_desc *meshes, int n_meshes, sphint_mode mode,
+                               void *workspace, size_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------ candidate lists (CSR) */
 
 /*

@@ -20,6 +20,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <new>
 #include <string>
 #include <vector>
@@ -94,11 +95,15 @@ namespace {
 
 template <int MODE, int PPT, bool CSR>
 int max_resident() {
-  int blocks = 0;
+  static std::atomic<int> cached{0};  // queried once; calls may come from several threads
+  int blocks = cached.load(std::memory_order_relaxed);
+  if (blocks) return blocks;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MODE, PPT, CSR>, BLOCK, 0) !=
-      hipSuccess)
-    return 1;
-  return blocks > 0 ? blocks : 1;
+          hipSuccess ||
+      blocks <= 0)
+    blocks = 1;
+  cached.store(blocks, std::memory_order_relaxed);
+  return blocks;
 }
 
 template <bool CSR>
@@ -409,4 +414,150 @@ extern "C" void sphint_plan_destroy(sphint_plan* p) {
   if (p->d_tile_base) (void)hipFree(p->d_tile_base);
   if (p->d_ws) (void)hipFree(p->d_ws);
   delete p;
+}
+
+// ------------------------------------------------------------ one-shot batched launch
+//
+// Continuous batching changes the set of meshes on every launch, so a plan (device tables,
+// a captured graph) would be rebuilt each time.  sphint_batch_run instead passes the
+// meshes' arguments to an init kernel by value; the init kernel writes them into the
+// caller's workspace, clears the tile states and fills the CSR pair-to-arc tables, and the
+// same persistent batched kernel as a plan's runs behind it.  Two launches, no allocation,
+// no host synchronisation.
+
+namespace {
+
+constexpr int RUN_MAX = SPHINT_BATCH_RUN_MAX;
+
+struct RunTable {
+  KArgs m[RUN_MAX];
+  int64_t tile_base[RUN_MAX + 1];
+};
+static_assert(sizeof(RunTable) <= 3584, "the table travels as a kernel argument");
+
+constexpr size_t RUN_ARGS_BYTES = (sizeof(KArgs) * RUN_MAX + 255) / 256 * 256;
+constexpr size_t RUN_BASE_BYTES = (sizeof(int64_t) * (RUN_MAX + 1) + 255) / 256 * 256;
+
+// Workspace layout: header (counter, error word) | argument table | tile bases | tile
+// states (one word per 64 pairs of each mesh, at most) | CSR pair-to-arc tables.
+size_t run_status_words(int n_meshes, int64_t total_nnz) {
+  return (size_t)((total_nnz + 63) / 64 + n_meshes + 1);
+}
+size_t run_workspace_bytes(int n_meshes, int64_t total_nnz) {
+  return WS_HEADER + RUN_ARGS_BYTES + RUN_BASE_BYTES + 8 * run_status_words(n_meshes, total_nnz) +
+         4 * (size_t)total_nnz;
+}
+
+__global__ __launch_bounds__(INIT_BLOCK) void k_batch_run_init(const RunTable tbl, int n_meshes,
+                                                               KArgs* __restrict__ d_args,
+                                                               int64_t* __restrict__ d_base,
+                                                               uint64_t* __restrict__ status,
+                                                               int64_t total_tiles,
+                                                               uint32_t* __restrict__ ws,
+                                                               int csr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    ws[0] = 0u;
+    ws[1] = 0u;
+  }
+  if (t < n_meshes) {
+    d_args[t] = tbl.m[t];
+    if (tbl.m[t].nnz == 0) *tbl.m[t].ototal = 0;
+  }
+  if (t <= n_meshes) d_base[t] = tbl.tile_base[t];
+  for (int64_t k = t; k < total_tiles; k += (int64_t)gridDim.x * blockDim.x) status[k] = 0ull;
+  if (!csr) return;
+  __shared__ uint32_t win[INIT_BLOCK / 64][FILL_W];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int m = 0; m < n_meshes; ++m) {  // every wavefront takes part in every mesh's fill
+    const KArgs& a = tbl.m[m];
+    if (a.nnz > 0)
+      fill_pair_arcs(a.off, a.n_arcs, a.nnz, const_cast<uint32_t*>(a.parc),
+                     (int64_t)blockIdx.x * (INIT_BLOCK / 64) + wave,
+                     (int64_t)gridDim.x * (INIT_BLOCK / 64), win[wave]);
+  }
+}
+
+// Pairs per lane of a one-shot batch: those of single calls.
+constexpr int run_ppt(sphint_mode mode) { return mode == SPHINT_EFT_FP64 ? 3 : 4; }
+
+template <int MODE, bool CSR>
+void launch_run(const KArgs* d_args, const int64_t* d_base, int n, int64_t total_tiles,
+                hipStream_t st) {
+  constexpr int PPT = MODE ? 3 : 4;
+  const int per_cu = max_resident<MODE, PPT, CSR>();
+  int64_t grid = (total_tiles + 1 + NWAVE - 1) / NWAVE;  // + the scanner
+  if ((int64_t)per_cu * device_cus() < grid) grid = (int64_t)per_cu * device_cus();
+  hipLaunchKernelGGL((k_batch<MODE, PPT, CSR>), dim3((unsigned)grid), dim3(BLOCK), 0, st, d_args,
+                     d_base, n, total_tiles);
+}
+
+}  // namespace
+
+extern "C" size_t sphint_batch_run_workspace_size(int n_meshes, int64_t total_nnz) {
+  if (n_meshes < 0 || total_nnz < 0) return 0;
+  return run_workspace_bytes(n_meshes, total_nnz);
+}
+
+extern "C" sphint_status sphint_batch_run(const sphint_mesh_desc* meshes, int n_meshes,
+                                          sphint_mode mode, void* workspace,
+                                          size_t workspace_bytes, void* stream) {
+  if (!meshes || n_meshes < 1 || n_meshes > RUN_MAX) return SPHINT_E_INVAL;
+  if (mode != SPHINT_NAIVE_FP64 && mode != SPHINT_EFT_FP64) return SPHINT_E_INVAL;
+  const bool csr = meshes[0].lat_offsets != nullptr;
+  int64_t total_nnz = 0;
+  for (int m = 0; m < n_meshes; ++m) {
+    const sphint_mesh_desc& d = meshes[m];
+    sphint_status v = validate(d.n_arcs, d.p1, d.p2, d.lat_z, d.n_lat, d.lat_offsets, d.lat_idx,
+                               d.nnz, d.out, d.out_count, d.out_total);
+    if (v != SPHINT_OK) return v;
+    if ((d.lat_offsets != nullptr) != csr) return SPHINT_E_INVAL;
+    total_nnz += d.nnz;
+  }
+  if (total_nnz > ((int64_t)1 << 40)) return SPHINT_E_INVAL;
+  if (!workspace || !aligned256(workspace) ||
+      workspace_bytes < run_workspace_bytes(n_meshes, total_nnz))
+    return SPHINT_E_INVAL;
+  const int ppt = run_ppt(mode);
+  RunTable tbl;
+  memset(&tbl, 0, sizeof(tbl));
+  char* w = (char*)workspace;
+  uint32_t* ws = (uint32_t*)w;
+  KArgs* d_args = (KArgs*)(w + WS_HEADER);
+  int64_t* d_base = (int64_t*)(w + WS_HEADER + RUN_ARGS_BYTES);
+  uint64_t* status = (uint64_t*)(w + WS_HEADER + RUN_ARGS_BYTES + RUN_BASE_BYTES);
+  uint32_t* parc = (uint32_t*)(status + run_status_words(n_meshes, total_nnz));
+  int64_t max_arcs = 0;
+  for (int m = 0; m < n_meshes; ++m) {
+    const sphint_mesh_desc& d = meshes[m];
+    const int64_t nt = wave_tiles_for(d.nnz, ppt);
+    tbl.tile_base[m + 1] = tbl.tile_base[m] + nt;
+    tbl.m[m] = make_args(d.n_arcs, d.p1, d.p2, d.lat_z, d.n_lat, d.lat_offsets, d.lat_idx, d.nnz,
+                         d.out, d.out_count, d.out_flags, d.out_total, ws,
+                         status + tbl.tile_base[m], nt, csr ? parc : nullptr);
+    if (csr) parc += d.nnz;
+    if (d.n_arcs > max_arcs) max_arcs = d.n_arcs;
+  }
+  for (int m = n_meshes; m < RUN_MAX; ++m) tbl.tile_base[m + 1] = tbl.tile_base[n_meshes];
+  const int64_t total_tiles = tbl.tile_base[n_meshes];
+  if (total_tiles > 0x7fffffffLL) return SPHINT_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  LaunchChain chain;
+  if (chain.begin(st) != hipSuccess) return SPHINT_E_HIP;
+  int64_t ib = (total_tiles + INIT_BLOCK - 1) / INIT_BLOCK;
+  if (csr && fill_blocks(max_arcs) > ib) ib = fill_blocks(max_arcs);
+  if (ib > 8192) ib = 8192;
+  if (ib < 1) ib = 1;
+  hipLaunchKernelGGL(k_batch_run_init, dim3((unsigned)ib), dim3(INIT_BLOCK), 0, st, tbl, n_meshes,
+                     d_args, d_base, status, total_tiles, ws, (int)csr);
+  if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
+  if (total_tiles > 0) {
+    const bool eft = mode == SPHINT_EFT_FP64;
+    if (csr) eft ? launch_run<1, true>(d_args, d_base, n_meshes, total_tiles, st)
+                 : launch_run<0, true>(d_args, d_base, n_meshes, total_tiles, st);
+    else eft ? launch_run<1, false>(d_args, d_base, n_meshes, total_tiles, st)
+             : launch_run<0, false>(d_args, d_base, n_meshes, total_tiles, st);
+    if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
+  }
+  return chain.end() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
 }

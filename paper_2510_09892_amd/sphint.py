@@ -24,6 +24,7 @@ F_FALLBACK, F_INTERNAL = 32, 64  # diagnostic bits of the EFT mode
 ROOT_PLUS, ROOT_MINUS = 0, 1
 F_RECOMPUTED = 128
 NOALLOC_SCRATCH_BYTES = 64 << 20  # SPHINT_NOALLOC_SCRATCH_BYTES
+BATCH_RUN_MAX = 16  # SPHINT_BATCH_RUN_MAX
 AA_HIT, AA_DEGEN, AA_COPLANAR, AA_NONFINITE, AA_EXACT, AA_INTERNAL = 1, 4, 8, 16, 32, 64
 
 EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
@@ -31,7 +32,7 @@ EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_set_profile_events",
            "sphint_batch_plan_create", "sphint_batch_autotune", "sphint_batch_launch",
            "sphint_batch_params", "sphint_batch_set_params", "sphint_batch_check",
-           "sphint_plan_destroy",
+           "sphint_plan_destroy", "sphint_batch_run_workspace_size", "sphint_batch_run",
            "sphint_candidates_workspace_size", "sphint_candidates_count",
            "sphint_candidates_fill",
            "sphint_arc_arc",
@@ -122,6 +123,11 @@ def load():
     lib.sphint_arc_constlat_adaptive.restype = ctypes.c_int
     lib.sphint_circle_points.argtypes = [i64, PtsSoA, PtsSoA, vp, ctypes.c_int, vp, vp, vp, vp]
     lib.sphint_circle_points.restype = ctypes.c_int
+    lib.sphint_batch_run_workspace_size.argtypes = [ctypes.c_int, i64]
+    lib.sphint_batch_run_workspace_size.restype = sz
+    lib.sphint_batch_run.argtypes = [ctypes.POINTER(MeshDesc), ctypes.c_int, ctypes.c_int, vp,
+                                     sz, vp]
+    lib.sphint_batch_run.restype = ctypes.c_int
     lib.sphint_plan_destroy.argtypes = [vp]
     lib.sphint_plan_destroy.restype = None
     lib.sphint_status_string.argtypes = [ctypes.c_int]
@@ -531,25 +537,63 @@ class KernelTimer:
         self.ev = []
 
 
+def mesh_descs(meshes):
+    """Validated sphint_mesh_desc array for meshes given as dicts of device tensors (p1, p2,
+    lat_z, optional lat_offsets/lat_idx) with an Output under "out"."""
+    arr = (MeshDesc * len(meshes))()
+    for k, m in enumerate(meshes):
+        off = m.get("lat_offsets")
+        s1, s2, n_arcs, nnz = _check_pairs(m["p1"], m["p2"], m["lat_z"], off, m.get("lat_idx"))
+        out = m["out"]
+        _check_output(out, nnz, m["lat_z"].device)
+        arr[k] = MeshDesc(n_arcs, len(m["lat_z"]), out.nnz, s1, s2, m["lat_z"].data_ptr(),
+                          off.data_ptr() if off is not None else None,
+                          m["lat_idx"].data_ptr() if off is not None else None,
+                          out.hits_struct(), out.count.data_ptr(),
+                          out.flags.data_ptr() if out.flags is not None else None,
+                          out.total.data_ptr())
+    return arr
+
+
+def batch_run_workspace_size(n_meshes, total_nnz):
+    """sphint_batch_run_workspace_size."""
+    return int(load().sphint_batch_run_workspace_size(int(n_meshes), int(total_nnz)))
+
+
+def batch_run(meshes, mode="eft", workspace=None, stream=None):
+    """Enqueue sphint_batch_run: up to BATCH_RUN_MAX meshes (dicts as for BatchPlan) in one
+    persistent launch without a plan.  Returns the workspace tensor (its header holds the
+    launch's error word for sphint_check); nothing is synchronised."""
+    import torch
+    if not 1 <= len(meshes) <= BATCH_RUN_MAX:
+        raise SphintError(f"batch_run takes 1..{BATCH_RUN_MAX} meshes")
+    arr = mesh_descs(meshes)
+    need = batch_run_workspace_size(len(meshes), sum(m["out"].nnz for m in meshes))
+    dev = meshes[0]["lat_z"].device
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    _req(workspace, torch.uint8, "workspace", dev)
+    if workspace.numel() < need:
+        raise SphintError(f"workspace of {workspace.numel()} bytes, {need} needed")
+    batch_run_raw(arr, len(meshes), mode, workspace.data_ptr(), workspace.numel(),
+                  _stream(stream).value)
+    return workspace
+
+
+def batch_run_raw(descs, n_meshes, mode, workspace, workspace_bytes, stream):
+    """sphint_batch_run on a MeshDesc array of raw device addresses (``stream`` a hipStream_t
+    value)."""
+    _check(load().sphint_batch_run(descs, n_meshes, MODES[mode], ctypes.c_void_p(workspace),
+                                   workspace_bytes, ctypes.c_void_p(stream)), "sphint_batch_run")
+
+
 class BatchPlan:
     """sphint_batch_* over a list of meshes (each a dict of device tensors + Output)."""
 
     def __init__(self, meshes, mode="eft"):
         lib = load()
         self._keep = meshes
-        arr = (MeshDesc * len(meshes))()
-        for k, m in enumerate(meshes):
-            off = m.get("lat_offsets")
-            s1, s2, n_arcs, nnz = _check_pairs(m["p1"], m["p2"], m["lat_z"], off,
-                                               m.get("lat_idx"))
-            out = m["out"]
-            _check_output(out, nnz, m["lat_z"].device)
-            arr[k] = MeshDesc(n_arcs, len(m["lat_z"]), out.nnz, s1, s2, m["lat_z"].data_ptr(),
-                              off.data_ptr() if off is not None else None,
-                              m["lat_idx"].data_ptr() if off is not None else None,
-                              out.hits_struct(), out.count.data_ptr(),
-                              out.flags.data_ptr() if out.flags is not None else None,
-                              out.total.data_ptr())
+        arr = mesh_descs(meshes)
         h = ctypes.c_void_p()
         _check(lib.sphint_batch_plan_create(arr, len(meshes), MODES[mode], ctypes.byref(h)),
                "sphint_batch_plan_create")

@@ -6,6 +6,9 @@
 * Graph replays, with eager work and synchronisations between them, all give the same
   bytes; the autotuner's cache file is written and read back.
 * One small mesh against the oracle.
+* The one-shot batched launch (sphint_batch_run, no plan) over 1, 7 and 16 meshes (CSR
+  with an empty mesh among them, and dense), reusing one workspace on one stream: every
+  mesh equals its single call, in both modes.
 """
 
 import os
@@ -184,3 +187,53 @@ def test_batch_dense_meshes(torch_cuda):
                 assert same(read(d["out"]), r), ppt
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("mode", ["eft", "naive"])
+def test_batch_run_equals_single_calls(torch_cuda, mode):
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    csr = make_meshes(16, seed_tag=47)
+    empty = inputs.random_mesh(inputs.rng(47, 99), 50, 3)
+    empty.lat_offsets[:] = 0
+    empty.lat_idx = empty.lat_idx[:0]
+    csr[5] = empty
+    dense = [inputs.ill_conditioned(n, seed_tag=48 + k) for k, n in enumerate((1, 640, 5_000, 70_001))]
+    ref = {}
+    for k, m in enumerate(csr):
+        d = to_dev(torch, m)
+        sphint.arc_constlat(d["p1"], d["p2"], d["lat_z"], d["lat_offsets"], d["lat_idx"],
+                            mode=mode, out=d["out"])
+        torch.cuda.synchronize()
+        d["out"].check()
+        ref[("csr", k)] = read(d["out"])
+    for k, P in enumerate(dense):
+        t = [torch.from_numpy(a).cuda() for a in P.soa()]
+        out = sphint.Output(len(P))
+        sphint.arc_constlat(tuple(t[:3]), tuple(t[3:6]), t[6], mode=mode, out=out)
+        torch.cuda.synchronize()
+        out.check()
+        ref[("dense", k)] = read(out)
+    ws = torch.empty(sphint.batch_run_workspace_size(16, sum(m.nnz for m in csr)),
+                     dtype=torch.uint8, device="cuda")
+    for sel in ([3], list(range(7)), list(range(16))):
+        devs = [to_dev(torch, csr[k]) for k in sel]
+        note(f"batch_run {mode}: {len(sel)} CSR meshes, {sum(csr[k].nnz for k in sel)} pairs")
+        sphint.batch_run(devs, mode=mode, workspace=ws)
+        torch.cuda.synchronize()
+        assert sphint.load().sphint_check(ws.data_ptr(), 0, 0) == sphint.OK
+        for k, d in zip(sel, devs):
+            got = read(d["out"])
+            for key, v in ref[("csr", k)].items():
+                assert np.array_equal(np.asarray(got[key]), np.asarray(v)), (k, key)
+    devs = []
+    for P in dense:
+        t = [torch.from_numpy(a).cuda() for a in P.soa()]
+        devs.append(dict(p1=tuple(t[:3]), p2=tuple(t[3:6]), lat_z=t[6], out=sphint.Output(len(P))))
+    note(f"batch_run {mode}: {len(dense)} dense meshes")
+    sphint.batch_run(devs, mode=mode, workspace=ws)
+    torch.cuda.synchronize()
+    for k, d in enumerate(devs):
+        got = read(d["out"])
+        for key, v in ref[("dense", k)].items():
+            assert np.array_equal(np.asarray(got[key]), np.asarray(v)), (k, key)

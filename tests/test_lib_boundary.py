@@ -120,6 +120,41 @@ def test_noalloc_rejects_before_launch(bad):
     assert _noalloc(**bad) == sphint.E_INVAL
 
 
+def test_batch_run_workspace_and_rejections():
+    """sphint_batch_run: workspace size, and rejections before any launch (no GPU)."""
+    lib = sphint.load()
+    # header, argument table, tile bases, one tile state per 64 pairs (+1 per mesh + 1), and
+    # the CSR pair-to-arc tables: grows by 4 bytes per pair plus 8 per 64 pairs
+    base = lib.sphint_batch_run_workspace_size(1, 0)
+    assert base > 256 and base % 8 == 0
+    assert lib.sphint_batch_run_workspace_size(1, 64) == base + 8 + 4 * 64
+    assert lib.sphint_batch_run_workspace_size(2, 64) == base + 16 + 4 * 64
+    assert lib.sphint_batch_run_workspace_size(-1, 0) == 0
+
+    def desc(csr=True, nnz=4, n_arcs=4):
+        d = sphint.MeshDesc()
+        d.n_arcs, d.n_lat, d.nnz = n_arcs, 4 if csr else n_arcs, nnz
+        d.p1, d.p2 = sphint.PtsSoA(1, 2, 3), sphint.PtsSoA(4, 5, 6)
+        d.lat_z = 7
+        d.lat_offsets, d.lat_idx = (8, 9) if csr else (None, None)
+        d.out = sphint.Hits(10, 11, 12, 13, 2 * nnz)
+        d.out_count, d.out_flags, d.out_total = 14, None, 15
+        return d
+
+    def call(descs, ws=256, wsb=1 << 30, mode=1):
+        arr = (sphint.MeshDesc * max(1, len(descs)))(*descs)
+        return lib.sphint_batch_run(arr, len(descs), mode, ws, wsb, None)
+
+    assert call([]) == sphint.E_INVAL                                   # no mesh
+    assert call([desc()] * 17) == sphint.E_INVAL                        # above the maximum
+    assert call([desc(True), desc(False)]) == sphint.E_INVAL            # mixed forms
+    assert call([desc(nnz=-1)]) == sphint.E_INVAL                       # a bad mesh
+    assert call([desc()], mode=5) == sphint.E_INVAL
+    assert call([desc()], ws=None) == sphint.E_INVAL
+    assert call([desc()], ws=260) == sphint.E_INVAL                     # misaligned
+    assert call([desc()], wsb=lib.sphint_batch_run_workspace_size(1, 4) - 1) == sphint.E_INVAL
+
+
 def test_batch_rejects_bad_arguments():
     lib = sphint.load()
     h = ctypes.c_void_p()
