@@ -116,6 +116,14 @@ def run_mode(torch, sphint, call, nnz, mode, steps, warmup):
     return dict(wall_s=t1 - t0, kernel_ms=kms, total=total, hitpairs=hitpairs, out=out)
 
 
+def csr_main_bytes(arcs_used, nnz, n_lat, hits):
+    """Algorithmic bytes of one CSR main-kernel launch: the endpoints of every arc that has a
+    candidate (48 B, read once; arcs without one need not be read), per pair its latitude
+    index (4 B), its arc id (4 B, from the pair-to-arc table) and its count and flags (2 B),
+    the latitude table, and 25 B per hit (x, y, pair, root)."""
+    return 48 * arcs_used + 10 * nnz + 8 * n_lat + BYTES_PER_HIT * hits
+
+
 def roofline(mode, r, pairs, bytes_launch, kernel, tag):
     """Binding roof of the dominant kernel from its mean duration (HIP events)."""
     kms = statistics.mean(r["kernel_ms"])
@@ -178,14 +186,22 @@ def latency_small(torch, sphint, inputs, reps=1000):
     dev = [torch.from_numpy(a).cuda() for a in P.soa()]
     out = sphint.Output(len(P))
     lat = []
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
     for r in range(reps + 10):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        if r >= 10:
+            ev[r - 10][0].record()
         sphint.arc_constlat(tuple(dev[:3]), tuple(dev[3:6]), dev[6], mode="eft", out=out)
+        if r >= 10:
+            ev[r - 10][1].record()
         torch.cuda.synchronize()
         if r >= 10:
             lat.append((time.perf_counter() - t0) * 1e6)
     lat.sort()
+    # device time of each call: HIP events on the call's stream around its launches
+    dev_us = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
     plan = sphint.BatchPlan([dict(p1=tuple(dev[:3]), p2=tuple(dev[3:6]), lat_z=dev[6], out=out)],
                             mode="eft")
     for _ in range(10):
@@ -199,8 +215,13 @@ def latency_small(torch, sphint, inputs, reps=1000):
     dt = (time.perf_counter() - t0) / n_rep
     plan.check()
     plan.close()
-    return dict(p50_us=lat[len(lat) // 2], p99_us=lat[int(len(lat) * 0.99) - 1], calls=reps,
-                graph_replay_us=dt * 1e6, graph_replay_pairs_per_s=len(P) / dt)
+    return dict(device_p50_us=dev_us[len(dev_us) // 2], device_p10_p90_us=[
+                    dev_us[int(0.1 * (len(dev_us) - 1))], dev_us[int(0.9 * (len(dev_us) - 1))]],
+                device_p99_us=dev_us[int(len(dev_us) * 0.99) - 1],
+                p50_us=lat[len(lat) // 2], p99_us=lat[int(len(lat) * 0.99) - 1], calls=reps,
+                graph_replay_us=dt * 1e6, graph_replay_pairs_per_s=len(P) / dt,
+                note="device_*: HIP events around each call on its stream (init and main "
+                     "launch); p50_us/p99_us: host enqueue to completion")
 
 
 def serving(torch, args, log):
@@ -214,16 +235,18 @@ def serving(torch, args, log):
     out = {"workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s "
                        f"({n} requests); request k uses payload k mod {len(pool)} of a pool drawn "
                        "from log-uniform 1e3..1e6 arcs x log-uniform 1..1000 latitudes (CSR "
-                       "candidates); 64 GiB device budget; 8 slots",
+                       "candidates); 64 GiB device budget; continuous batching: up to 16 "
+                       "requests per persistent launch, 2 launches in flight, 32 request slots",
            "pool_pairs_mean": sum(p.nnz for p in pool) / len(pool)}
     for mode in ("eft", "naive"):
-        srv = serve.Server(mode=mode, budget_bytes=64 << 30, slots=8)
+        srv = serve.Server(mode=mode, budget_bytes=64 << 30, slots=32)
         srv.run(arrivals[:64] * 0.0, lambda i: pool[i % len(pool)])  # warm-up: arenas, code
         log(f"[bench] serving {mode}: {n} requests")
-        rep = srv.run(arrivals, lambda i: pool[i % len(pool)], check_every=97)
+        rep = srv.run(arrivals, lambda i: pool[i % len(pool)])
         srv.close()
         log(f"[bench] serving {mode}: {rep['req_per_s']:.0f} req/s, p50 {rep['latency_ms']['p50']:.3f} ms, "
-            f"p99 {rep['latency_ms']['p99']:.3f} ms")
+            f"p99 {rep['latency_ms']['p99']:.3f} ms, {rep['launches']} launches, "
+            f"{rep['requests_per_launch_mean']:.2f} requests per launch")
         out[mode] = rep
     return out
 
@@ -245,6 +268,127 @@ def candidate_timing(torch, sphint, inputs, mesh, dp, lz, reps=10):
     return {"gpu_ms": gpu_s * 1e3, "host_numpy_s": host_s, "arcs": len(mesh.p1),
             "candidates_gpu": int(len(idx)), "candidates_host": int(len(idx_h)),
             "arcs_per_s_gpu": len(mesh.p1) / gpu_s}
+
+
+def cubed_subresult(torch, np, sphint, inputs, steps, warmup):
+    """The regridding-shaped workload (ne = 1024 cubed sphere x 1800 latitudes, CSR) in both
+    modes: wall time per call, main-kernel time (HIP events) and its roofline."""
+    log("[bench] cubed sphere ne=1024 x 1800 latitudes: generating")
+    mesh = inputs.cubed_sphere(1024)
+    n = mesh.nnz
+    dp = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in mesh.soa()]
+    lz, off, idx = (torch.from_numpy(a).cuda() for a in (mesh.lat_z, mesh.lat_offsets, mesh.lat_idx))
+
+    def call(out, mode):
+        sphint.arc_constlat(tuple(dp[:3]), tuple(dp[3:]), lz, off, idx, mode=mode, out=out)
+    arcs_used = int(np.count_nonzero(np.diff(mesh.lat_offsets)))
+    res = {"workload": "cubed sphere ne=1024: 12,582,912 unique great-circle edges x 1800 "
+                       "latitude lines (-89.95 deg + 0.1 deg k), CSR candidates from z-range "
+                       "overlap", "pairs": n, "arcs": mesh.n_arcs, "arcs_with_candidates": arcs_used}
+    for mode in ("eft", "naive"):
+        r = run_mode(torch, sphint, call, n, mode, steps, warmup)
+        byts = csr_main_bytes(arcs_used, n, len(mesh.lat_z), r["total"])
+        kern = f"sphint::k_intersect_w<{1 if mode == 'eft' else 0},{3 if mode == 'eft' else 4},true>"
+        roof = roofline(mode, r, n, byts, kern, f"k_intersect_w_{mode}_cubed1024")
+        if roof.get("traffic"):
+            roof["traffic_over_algorithmic"] = roof["traffic"] / byts
+        res[mode] = {"value": n * steps / r["wall_s"], "ms_per_step": r["wall_s"] / steps * 1e3,
+                     "kernel_ms": statistics.mean(r["kernel_ms"]), "hits": r["total"],
+                     "roofline": roof}
+        log(f"[bench] cubed {mode}: {res[mode]['ms_per_step']:.4f} ms per call, kernel "
+            f"{res[mode]['kernel_ms']:.4f} ms, {roof['bound']} frac {roof['frac']:.3f}")
+        del r["out"]
+    res["eft_over_naive"] = res["eft"]["value"] / res["naive"]["value"]
+    return res
+
+
+def batch_measure(torch, sphint, devs, stats, modes, steps, warmup):
+    """One autotuned persistent graph launch over all meshes against one sphint_arc_constlat
+    call per mesh; `stats` per mesh: (arcs, arcs with candidates, pairs, latitudes)."""
+    nnz = sum(st[2] for st in stats)
+    res = {}
+    for mode in modes:
+        def per_mesh():
+            for d in devs:
+                sphint.arc_constlat(d["p1"], d["p2"], d["lat_z"], d["lat_offsets"], d["lat_idx"],
+                                    mode=mode, out=d["out"])
+        for _ in range(warmup):
+            per_mesh()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            per_mesh()
+        torch.cuda.synchronize()
+        t_per = (time.perf_counter() - t0) / steps
+        plan = sphint.BatchPlan(devs, mode=mode)
+        t1 = time.perf_counter()
+        plan.autotune()
+        t_tune = time.perf_counter() - t1
+        for _ in range(warmup):
+            plan.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.launch()
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / steps
+        # device time of each graph launch (HIP events on the launch stream around it)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for e0, e1 in ev:
+            e0.record()
+            plan.launch()
+            e1.record()
+        torch.cuda.synchronize()
+        dms = [e0.elapsed_time(e1) for e0, e1 in ev]
+        plan.check()
+        hits = sum(int(d["out"].total.item()) for d in devs)
+        hitpairs = sum(int((d["out"].count > 0).sum().item()) for d in devs)
+        # algorithmic bytes of one launch: the endpoints of arcs with candidates and the
+        # offsets, per pair its latitude index and its count and flags, the latitude tables,
+        # and the hits; the binding roof (HBM or binary64 ALU) of the whole graph launch,
+        # whose batched kernel dominates it
+        byts = sum(48 * st[1] + 8 * (st[0] + 1) + 6 * st[2] + 8 * st[3] for st in stats) \
+            + BYTES_PER_HIT * hits
+        kname = (f"graph launch: k_batch<{1 if mode == 'eft' else 0},{plan.params()[0]},true> "
+                 "with its init and pair-to-arc launches")
+        roof = roofline(mode, {"kernel_ms": dms, "total": hits, "hitpairs": hitpairs}, nnz, byts,
+                        kname, None)
+        res[mode] = dict(ms_per_step=t_batch * 1e3, device_ms=statistics.mean(dms),
+                         per_mesh_ms=t_per * 1e3, speedup_vs_per_mesh=t_per / t_batch,
+                         params=plan.params(), autotune_s=t_tune, hits=hits,
+                         value=nnz / t_batch, roofline=roof)
+        plan.close()
+        log(f"[bench] batch {mode}: {t_batch * 1e3:.2f} ms (per-mesh launches {t_per * 1e3:.2f} ms), "
+            f"params {res[mode]['params']}")
+    return res
+
+
+def batch_subresult(torch, sphint, inputs, steps, warmup):
+    """The 64-mesh batch with arcs drawn on the device and CSR lists built by the library's
+    candidate kernels (the host generator would take minutes for 7e7 arcs)."""
+    log("[bench] 64-mesh batch: drawing arcs and candidate lists on the device")
+    devs = inputs.device_mesh_arcs(torch, 64, seed_tag=3)
+    stats = []
+    for d in devs:
+        d["lat_offsets"], d["lat_idx"] = sphint.candidates(d["p1"], d["p2"], d["lat_z"])
+        d["out"] = sphint.Output(len(d["lat_idx"]))
+        n_arcs = len(d["p1"][0])
+        used = int((d["lat_offsets"][1:] > d["lat_offsets"][:-1]).sum().item())
+        stats.append((n_arcs, used, len(d["lat_idx"]), len(d["lat_z"])))
+    torch.cuda.synchronize()
+    nnz = sum(st[2] for st in stats)
+    log(f"[bench] batch: 64 meshes, {sum(st[0] for st in stats)} arcs, {nnz} pairs")
+    res = batch_measure(torch, sphint, devs, stats, ("eft", "naive"), steps, warmup)
+    out = {"workload": "64 meshes, log-uniform 1e3..1e7 arcs (d ~ U[1e-3, 0.05] rad, drawn on "
+                       "the device) x U{10..3600} latitudes, CSR lists from the GPU candidate "
+                       "kernels; one autotuned persistent hipGraph launch against 64 per-mesh calls",
+           "meshes": 64, "arcs": sum(st[0] for st in stats), "pairs": nnz}
+    out.update(res)
+    out["eft_over_naive"] = res["eft"]["value"] / res["naive"]["value"]
+    for d in devs:
+        d.clear()
+    return out
 
 
 def cpu_model():
@@ -271,7 +415,7 @@ def cpu_baseline(P, inputs, sample):
     t1 = time.perf_counter()
     OB.exact(*S1.soa(), workers=1)
     d1 = time.perf_counter() - t1
-    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "kind": "oracle",
+    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"{len(S)} pairs, stratified over the 3 parts of the same workload "
                       f"(exact integer predicates + 100-digit decimal points), {dt:.1f} s wall",
             "single_core_value": len(S1) / d1, "cpu_model": cpu_model()}
@@ -285,7 +429,7 @@ def cpu_baseline_dense(P, sample, what):
     t0 = time.perf_counter()
     OB.exact(*S.soa(), workers=workers)
     dt = time.perf_counter() - t0
-    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "kind": "oracle",
+    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"{len(S)} pairs, {what} (exact integer predicates + 100-digit decimal "
                       f"points), {dt:.1f} s wall", "cpu_model": cpu_model()}
 
@@ -349,7 +493,7 @@ def cpu_baseline_csr(meshes, inputs, sample):
     t0 = time.perf_counter()
     OB.exact(*S.soa(), workers=workers)
     dt = time.perf_counter() - t0
-    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "kind": "oracle",
+    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"{len(S)} candidate pairs drawn uniformly from the workload's CSR lists "
                       f"(exact integer predicates + 100-digit decimal points), {dt:.1f} s wall"}
 
@@ -373,6 +517,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-subresults", action="store_true",
+                    help="skip the cubed-sphere and 64-mesh sub-results of the default line")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-pool", type=int, default=64)
@@ -434,10 +580,9 @@ def main():
 
         def call(out, mode):
             sphint.arc_constlat(tuple(dp[:3]), tuple(dp[3:]), lz, off, idx, mode=mode, out=out)
-        # what the main kernel reads and writes once: endpoints, each pair's arc (the
-        # pair-to-arc table the init launch writes from the offsets), latitude indices, the
-        # latitude table, counts and flags (+ hits below)
-        bytes_in = 48 * mesh.n_arcs + 4 * n + 4 * n + 8 * len(mesh.lat_z) + 2 * n
+        # what the main kernel reads and writes once (hits added below)
+        bytes_in = csr_main_bytes(int(np.count_nonzero(np.diff(mesh.lat_offsets))), n,
+                                  len(mesh.lat_z), 0)
         csr = True
     torch.cuda.synchronize()
 
@@ -491,6 +636,9 @@ def main():
         line["latency_1e5"] = latency_small(torch, sphint, inputs)
     if not args.no_serve and args.workload == "ill1e7":
         line["serving"] = serving(torch, args, log)
+    if not args.no_subresults and args.workload == "ill1e7":
+        line["cubed_sphere"] = cubed_subresult(torch, np, sphint, inputs, 10, 3)
+        line["batch64"] = batch_subresult(torch, sphint, inputs, 5, 2)
     if args.workload == "cubed1024":
         log("[bench] candidate lists on the GPU and on the host")
         line["candidates"] = candidate_timing(torch, sphint, inputs, mesh, dp, lz)
@@ -522,60 +670,9 @@ def bench_batch(args, torch, np, inputs, sphint):
                          lat_offsets=torch.from_numpy(m.lat_offsets).cuda(),
                          lat_idx=torch.from_numpy(m.lat_idx).cuda(), out=sphint.Output(m.nnz)))
     log(f"[bench] batch: 64 meshes, {sum(m.n_arcs for m in meshes)} arcs, {nnz} pairs on the device")
-    res = {}
-    for mode in args.modes.split(","):
-        def per_mesh():
-            for d in devs:
-                sphint.arc_constlat(d["p1"], d["p2"], d["lat_z"], d["lat_offsets"], d["lat_idx"],
-                                    mode=mode, out=d["out"])
-        for _ in range(args.warmup):
-            per_mesh()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            per_mesh()
-        torch.cuda.synchronize()
-        t_per = (time.perf_counter() - t0) / args.steps
-        plan = sphint.BatchPlan(devs, mode=mode)
-        t1 = time.perf_counter()
-        plan.autotune()
-        t_tune = time.perf_counter() - t1
-        for _ in range(args.warmup):
-            plan.launch()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            plan.launch()
-        torch.cuda.synchronize()
-        t_batch = (time.perf_counter() - t0) / args.steps
-        # device time of each graph launch (HIP events on the launch stream around it)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-        for e0, e1 in ev:
-            e0.record()
-            plan.launch()
-            e1.record()
-        torch.cuda.synchronize()
-        dms = [e0.elapsed_time(e1) for e0, e1 in ev]
-        plan.check()
-        hits = sum(int(d["out"].total.item()) for d in devs)
-        hitpairs = sum(int((d["out"].count > 0).sum().item()) for d in devs)
-        # algorithmic bytes of one launch: endpoints and offsets per arc, latitude index,
-        # count and flags per pair, the latitude tables, and the hits; the binding roof (HBM
-        # or binary64 ALU) of the whole graph launch, whose batched kernel dominates it
-        byts = sum(48 * m.n_arcs + 8 * (m.n_arcs + 1) + 6 * m.nnz + 8 * len(m.lat_z)
-                   for m in meshes) + BYTES_PER_HIT * hits
-        kname = (f"graph launch: k_batch<{1 if mode == 'eft' else 0},{plan.params()[0]},true> "
-                 "with its init and pair-to-arc launches")
-        roof = roofline(mode, {"kernel_ms": dms, "total": hits, "hitpairs": hitpairs}, nnz, byts,
-                        kname, None)
-        res[mode] = dict(ms_per_step=t_batch * 1e3, device_ms=statistics.mean(dms),
-                         per_mesh_ms=t_per * 1e3, speedup_vs_per_mesh=t_per / t_batch,
-                         params=plan.params(), autotune_s=t_tune, hits=hits,
-                         value=nnz / t_batch, roofline=roof)
-        plan.close()
-        log(f"[bench] batch {mode}: {t_batch * 1e3:.2f} ms (per-mesh launches {t_per * 1e3:.2f} ms), "
-            f"params {res[mode]['params']}")
+    stats = [(m.n_arcs, int(np.count_nonzero(np.diff(m.lat_offsets))), m.nnz, len(m.lat_z))
+             for m in meshes]
+    res = batch_measure(torch, sphint, devs, stats, args.modes.split(","), args.steps, args.warmup)
     head = "eft" if "eft" in res else next(iter(res))
     r = res[head]
     line = {
@@ -618,7 +715,7 @@ def cpu_baseline_arcarc(P, sample):
     t0 = time.perf_counter()
     OB.arcarc_exact(S.a1, S.a2, S.b1, S.b2, workers=workers)
     dt = time.perf_counter() - t0
-    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "kind": "oracle",
+    return {"value": len(S) / dt, "unit": "intersections/s", "cores": workers, "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"{len(S)} pairs, the first {sample // 4} of each of the 4 parts of the same "
                       f"workload (exact integer orientations + 100-digit decimal points), "
                       f"{dt:.1f} s wall", "cpu_model": cpu_model()}

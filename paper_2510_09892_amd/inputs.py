@@ -15,7 +15,10 @@ Workloads (sizes are defaults; tests pass smaller ones):
   (c) both endpoints within 1e-6 rad of a pole, z0 in the z-range.
 * ``cubed_sphere``   all unique edges of an equiangular gnomonic cubed sphere with ne x ne
   cells per face, plus latitude lines, and CSR candidate lists from z-range overlap.
-* ``mesh_batch`` / ``request_stream``: many uneven meshes for batched and served runs.
+* ``mesh_batch`` / ``request_stream``: many uneven meshes for batched and served runs;
+  ``device_arcs`` / ``device_mesh_batch`` draw the same shapes on the GPU with torch's
+  seeded generator (the 64-mesh batch holds 7e7 arcs, too many to draw on the host in a
+  benchmark run).
 * ``arc_pairs``      arc x arc pairs in four equal parts: crossing-shaped arcs (B through a
   point near A's midpoint, about half of them cross), short arcs (1e-9 to 1e-6 rad), nearly
   parallel arcs (endpoints tilted by 1e-9 to 1e-3) and mesh-like shared vertices (b1 = a2
@@ -399,3 +402,49 @@ def arc_pairs(n: int = 10_000_000, seed_tag: int = 5) -> ArcPairs:
     out.append((a1, a2, a2.copy(), b2))
     part = np.concatenate([np.full(sz, k, np.int8) for k, sz in enumerate(sizes)])
     return ArcPairs(*(np.concatenate([o[i] for o in out]) for i in range(4)), part=part)
+
+
+# ----------------------------------------------------------- drawn on the device
+
+def device_arcs(torch, gen, n: int, d_lo: float = 1e-3, d_hi: float = 0.05):
+    """As ``arc_from`` on uniform points, drawn on the current CUDA device: p1 uniform on the
+    sphere, p2 at distance d ~ U[d_lo, d_hi] along a uniform bearing.  Returns the (x, y, z)
+    components of p1 and p2 as contiguous float64 device tensors."""
+    import math
+    f64 = dict(dtype=torch.float64, device="cuda")
+    p = torch.randn(n, 3, generator=gen, **f64)
+    p = p / p.norm(dim=1, keepdim=True)
+    d = d_lo + (d_hi - d_lo) * torch.rand(n, generator=gen, **f64)
+    b = 2 * math.pi * torch.rand(n, generator=gen, **f64)
+    x, y, z = p[:, 0], p[:, 1], p[:, 2]
+    r = torch.hypot(x, y)
+    east = torch.stack([-y / r, x / r, torch.zeros_like(r)], dim=1)
+    north = torch.stack([-z * x / r, -z * y / r, r], dim=1)
+    t = torch.cos(b)[:, None] * north + torch.sin(b)[:, None] * east
+    q = torch.cos(d)[:, None] * p + torch.sin(d)[:, None] * t
+    return [p[:, k].contiguous() for k in range(3)], [q[:, k].contiguous() for k in range(3)]
+
+
+def device_mesh_sizes(n_meshes: int = 64, arcs_lo: float = 1e3, arcs_hi: float = 1e7,
+                      lat_lo: int = 10, lat_hi: int = 3600, seed_tag: int = 3):
+    """Arcs (log-uniform) and latitude counts (uniform) of the uneven mesh batch."""
+    g = rng(seed_tag)
+    sizes = np.floor(np.exp(g.uniform(np.log(arcs_lo), np.log(arcs_hi), n_meshes))).astype(int)
+    lats = g.integers(lat_lo, lat_hi + 1, n_meshes)
+    return sizes, lats
+
+
+def device_mesh_arcs(torch, n_meshes: int = 64, seed_tag: int = 3):
+    """The uneven batch's arcs and latitude tables drawn on the device, one dict per mesh
+    with p1, p2 (component tensors) and lat_z (L uniformly spaced latitude lines at
+    -90 + (k + 1/2) 180 / L degrees).  Candidate lists are left to the caller."""
+    sizes, lats = device_mesh_sizes(n_meshes, seed_tag=seed_tag)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(SEED_BASE + seed_tag)
+    out = []
+    for n, L in zip(sizes, lats):
+        p1, p2 = device_arcs(torch, gen, int(n))
+        step = 180.0 / int(L)
+        lat_z = torch.from_numpy(latitude_lines(int(L), -90.0 + step / 2, step)).cuda()
+        out.append(dict(p1=tuple(p1), p2=tuple(p2), lat_z=lat_z))
+    return out

@@ -12,7 +12,6 @@ configuration (one autotuned persistent graph launch):
   AccuX replica (points, within 4 * 2^-53).
 """
 
-import math
 from decimal import Decimal
 
 import numpy as np
@@ -38,41 +37,17 @@ def torch_cuda():
     return torch
 
 
-def device_arcs(torch, gen, n, d_lo=1e-3, d_hi=0.05):
-    """p1 uniform on the sphere, p2 at distance d ~ U[d_lo, d_hi] along a uniform bearing."""
-    f64 = dict(dtype=torch.float64, device="cuda")
-    p = torch.randn(n, 3, generator=gen, **f64)
-    p = p / p.norm(dim=1, keepdim=True)
-    d = d_lo + (d_hi - d_lo) * torch.rand(n, generator=gen, **f64)
-    b = 2 * math.pi * torch.rand(n, generator=gen, **f64)
-    x, y, z = p[:, 0], p[:, 1], p[:, 2]
-    r = torch.hypot(x, y)
-    east = torch.stack([-y / r, x / r, torch.zeros_like(r)], dim=1)
-    north = torch.stack([-z * x / r, -z * y / r, r], dim=1)
-    t = torch.cos(b)[:, None] * north + torch.sin(b)[:, None] * east
-    q = torch.cos(d)[:, None] * p + torch.sin(d)[:, None] * t
-    return [p[:, k].contiguous() for k in range(3)], [q[:, k].contiguous() for k in range(3)]
-
-
 @pytest.fixture(scope="module")
 def meshes(torch_cuda):
     from paper_2510_09892_amd import sphint
     torch = torch_cuda
-    g = inputs.rng(3)
-    sizes = np.floor(np.exp(g.uniform(np.log(1e3), np.log(1e7), 64))).astype(int)
-    lats = g.integers(10, 3601, 64)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(inputs.SEED_BASE + 3)
-    out = []
-    for k, (n, L) in enumerate(zip(sizes, lats)):
-        p1, p2 = device_arcs(torch, gen, int(n))
-        step = 180.0 / int(L)
-        lat_z = torch.from_numpy(inputs.latitude_lines(int(L), -90.0 + step / 2, step)).cuda()
-        off, idx = sphint.candidates(tuple(p1), tuple(p2), lat_z)
-        out.append(dict(p1=tuple(p1), p2=tuple(p2), lat_z=lat_z, lat_offsets=off, lat_idx=idx,
-                        out=sphint.Output(len(idx))))
+    out = inputs.device_mesh_arcs(torch, 64, seed_tag=3)
+    for m in out:
+        m["lat_offsets"], m["lat_idx"] = sphint.candidates(m["p1"], m["p2"], m["lat_z"])
+        m["out"] = sphint.Output(len(m["lat_idx"]))
     torch.cuda.synchronize()
-    note(f"64 meshes: {int(sizes.sum())} arcs, {sum(len(m['lat_idx']) for m in out)} pairs")
+    note(f"64 meshes: {sum(len(m['p1'][0]) for m in out)} arcs, "
+         f"{sum(len(m['lat_idx']) for m in out)} pairs")
     return out
 
 
