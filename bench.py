@@ -350,13 +350,14 @@ def batch_measure(torch, sphint, devs, stats, modes, steps, warmup):
         # whose batched kernel dominates it
         byts = sum(48 * st[1] + 8 * (st[0] + 1) + 6 * st[2] + 8 * st[3] for st in stats) \
             + BYTES_PER_HIT * hits
-        kname = (f"graph launch: k_batch<{1 if mode == 'eft' else 0},{plan.params()[0]},true> "
-                 "with its init and pair-to-arc launches")
+        lb = plan.lookback()
+        kname = (f"graph launch: k_batch<{1 if mode == 'eft' else 0},{plan.params()[0]},true,"
+                 f"{'true' if lb else 'false'}> with its init and pair-to-arc launches")
         roof = roofline(mode, {"kernel_ms": dms, "total": hits, "hitpairs": hitpairs}, nnz, byts,
                         kname, None)
         res[mode] = dict(ms_per_step=t_batch * 1e3, device_ms=statistics.mean(dms),
                          per_mesh_ms=t_per * 1e3, speedup_vs_per_mesh=t_per / t_batch,
-                         params=plan.params(), autotune_s=t_tune, hits=hits,
+                         params=plan.params(), lookback=lb, autotune_s=t_tune, hits=hits,
                          value=nnz / t_batch, roofline=roof)
         plan.close()
         log(f"[bench] batch {mode}: {t_batch * 1e3:.2f} ms (per-mesh launches {t_per * 1e3:.2f} ms), "

@@ -203,8 +203,9 @@ typedef struct sphint_plan sphint_plan;
  */
 sphint_status sphint_batch_plan_create(const sphint_mesh_desc *meshes, int n_meshes,
                                        sphint_mode mode, sphint_plan **plan);
-/* Times the plan's candidate schedules (pairs per thread 1-4 x persistent grid sizes)
- * by running the whole batch on `stream`, keeps the fastest, and synchronizes the stream;
+/* Times the plan's candidate schedules (pairs per thread 1-4 x persistent grid sizes x the
+ * two ways of ordering tile offsets, see sphint_batch_set_scan) by running the whole batch
+ * on `stream`, keeps the fastest, and synchronizes the stream;
  * reads/appends a text cache at cache_path (may be NULL) keyed by the plan's shape.  The
  * batch's outputs are overwritten (with the same values). */
 sphint_status sphint_batch_autotune(sphint_plan *plan, const char *cache_path, void *stream);
@@ -219,6 +220,13 @@ sphint_status sphint_batch_params(const sphint_plan *plan, int *pairs_per_thread
 /* Sets the schedule by hand (pairs_per_thread 1 to 4; wg_per_cu >= 0, capped at what a CU
  * holds) instead of the autotuner's choice; the next launch re-captures the graph. */
 sphint_status sphint_batch_set_params(sphint_plan *plan, int pairs_per_thread, int wg_per_cu);
+/* How tiles learn their offsets in the compacted outputs: 0 = one scanner wavefront turns the
+ * tiles' hit counts into prefixes in tile order; 1 = decoupled look-back (each wavefront sums
+ * its predecessors' counts back to the nearest published inclusive prefix and publishes its
+ * own), which spares small tiles the wait on one scanner.  Results are identical.  Setting
+ * it re-captures the graph at the next launch. */
+sphint_status sphint_batch_scan(const sphint_plan *plan, int *lookback);
+sphint_status sphint_batch_set_scan(sphint_plan *plan, int lookback);
 /* After the stream has completed a launch of the plan: SPHINT_E_DEVICE if a kernel of that
  * launch reported an internal limit (as sphint_check), else SPHINT_E_CAPACITY if some mesh's
  * *out_total exceeds its out.capacity, else SPHINT_OK.  Synchronous (reads the plan's error

@@ -8,8 +8,10 @@
 // mesh alone.  The scanner wavefront publishes the in-order prefixes of mesh 0's tiles, then
 // mesh 1's, and so on.
 //
-// Schedule parameters: pairs per lane (wavefront tile = 64 * ppt pairs) and the number of
-// resident workgroups per CU; sphint_batch_autotune times the candidates and keeps the
+// Schedule parameters: pairs per lane (wavefront tile = 64 * ppt pairs), the number of
+// resident workgroups per CU, and how tiles learn their output offsets (the scanner
+// wavefront, or decoupled look-back by every wavefront, which lets small tiles run without
+// waiting on one scanner); sphint_batch_autotune times the candidates and keeps the
 // fastest.  The init kernel and the persistent kernel are captured once into a HIP graph and
 // replayed.
 #pragma clang fp contract(off)
@@ -29,7 +31,7 @@
 
 using namespace sphint;
 
-template <int MODE, int PPT, bool CSR>
+template <int MODE, int PPT, bool CSR, bool LB>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(const KArgs* __restrict__ args,
                                                  const int64_t* __restrict__ tile_base,
                                                  int n_meshes, int64_t total_tiles) {
@@ -38,8 +40,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
   const int64_t gw = (int64_t)blockIdx.x * NWAVE + wave;
-  const int64_t W = (int64_t)gridDim.x * NWAVE - 1;
-  if (gw == W) {  // the scanner follows the global tile order: mesh after mesh
+  const int64_t W = (int64_t)gridDim.x * NWAVE - (LB ? 0 : 1);
+  if (!LB && gw == W) {  // the scanner follows the global tile order: mesh after mesh
     for (int m = 0; m < n_meshes; ++m) {
       const KArgs a = args[m];
       scan_tiles<scan_k<PPT>()>(a.status, a.ntiles, a.ototal, a.ws,
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   }
   int64_t t = gw;
   int mesh = 0;  // tiles only increase, so the mesh index only moves forward
-  wave_loop<MODE, PPT, CSR, flush_at<MODE, PPT>()>(args, sh, [&](int& m, int64_t& tile) {
+  wave_loop<MODE, PPT, CSR, flush_at<MODE, PPT>(), LB>(args, sh, [&](int& m, int64_t& tile) {
     if (t >= total_tiles) return false;
     while (mesh + 1 < n_meshes && tile_base[mesh + 1] <= t) ++mesh;
     m = mesh;
@@ -78,6 +80,7 @@ struct sphint_plan {
   // schedule
   int ppt = 1;
   int wg_per_cu = 0;  // resident workgroups per CU (0: as many as fit)
+  bool lookback = false;  // tile offsets by decoupled look-back instead of the scanner
   // device state
   KArgs* d_args = nullptr;
   int64_t* d_tile_base = nullptr;
@@ -93,12 +96,12 @@ struct sphint_plan {
 
 namespace {
 
-template <int MODE, int PPT, bool CSR>
+template <int MODE, int PPT, bool CSR, bool LB = false>
 int max_resident() {
   static std::atomic<int> cached{0};  // queried once; calls may come from several threads
   int blocks = cached.load(std::memory_order_relaxed);
   if (blocks) return blocks;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MODE, PPT, CSR>, BLOCK, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MODE, PPT, CSR, LB>, BLOCK, 0) !=
           hipSuccess ||
       blocks <= 0)
     blocks = 1;
@@ -106,18 +109,18 @@ int max_resident() {
   return blocks;
 }
 
-template <bool CSR>
+template <bool CSR, bool LB>
 int resident_per_cu_form(sphint_mode mode, int ppt) {
   if (mode == SPHINT_EFT_FP64) {
-    if (ppt == 1) return max_resident<1, 1, CSR>();
-    if (ppt == 2) return max_resident<1, 2, CSR>();
-    if (ppt == 3) return max_resident<1, 3, CSR>();
-    return max_resident<1, 4, CSR>();
+    if (ppt == 1) return max_resident<1, 1, CSR, LB>();
+    if (ppt == 2) return max_resident<1, 2, CSR, LB>();
+    if (ppt == 3) return max_resident<1, 3, CSR, LB>();
+    return max_resident<1, 4, CSR, LB>();
   }
-  if (ppt == 1) return max_resident<0, 1, CSR>();
-  if (ppt == 2) return max_resident<0, 2, CSR>();
-  if (ppt == 3) return max_resident<0, 3, CSR>();
-  return max_resident<0, 4, CSR>();
+  if (ppt == 1) return max_resident<0, 1, CSR, LB>();
+  if (ppt == 2) return max_resident<0, 2, CSR, LB>();
+  if (ppt == 3) return max_resident<0, 3, CSR, LB>();
+  return max_resident<0, 4, CSR, LB>();
 }
 
 void drop_graph(sphint_plan* p) {
@@ -165,19 +168,28 @@ sphint_status layout(sphint_plan* p) {
   return SPHINT_OK;
 }
 
-int resident_per_cu(const sphint_plan* p, int ppt) {
-  return p->csr ? resident_per_cu_form<true>(p->mode, ppt)
-                : resident_per_cu_form<false>(p->mode, ppt);
+int resident_per_cu(const sphint_plan* p, int ppt, bool lb) {
+  if (lb)
+    return p->csr ? resident_per_cu_form<true, true>(p->mode, ppt)
+                  : resident_per_cu_form<false, true>(p->mode, ppt);
+  return p->csr ? resident_per_cu_form<true, false>(p->mode, ppt)
+                : resident_per_cu_form<false, false>(p->mode, ppt);
+}
+
+template <int MODE, int PPT, bool LB>
+void launch_batch_lb(const sphint_plan* p, unsigned grid, hipStream_t st) {
+  if (p->csr)
+    hipLaunchKernelGGL((k_batch<MODE, PPT, true, LB>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
+                       p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
+  else
+    hipLaunchKernelGGL((k_batch<MODE, PPT, false, LB>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
+                       p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
 }
 
 template <int MODE, int PPT>
 void launch_batch(const sphint_plan* p, unsigned grid, hipStream_t st) {
-  if (p->csr)
-    hipLaunchKernelGGL((k_batch<MODE, PPT, true>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
-                       p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
-  else
-    hipLaunchKernelGGL((k_batch<MODE, PPT, false>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
-                       p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
+  if (p->lookback) launch_batch_lb<MODE, PPT, true>(p, grid, st);
+  else launch_batch_lb<MODE, PPT, false>(p, grid, st);
 }
 
 // Enqueues init + persistent kernel on st (no graph).
@@ -201,9 +213,9 @@ sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
     }
   if (p->total_tiles > 0) {
     // every wavefront of the grid must be resident at once (see k_batch)
-    const int res = resident_per_cu(p, p->ppt);
+    const int res = resident_per_cu(p, p->ppt, p->lookback);
     const int per_cu = p->wg_per_cu > 0 && p->wg_per_cu < res ? p->wg_per_cu : res;
-    int64_t grid = (p->total_tiles + 1 + NWAVE - 1) / NWAVE;  // + the scanner
+    int64_t grid = (p->total_tiles + (p->lookback ? 0 : 1) + NWAVE - 1) / NWAVE;  // + scanner
     if ((int64_t)per_cu * p->cus < grid) grid = (int64_t)per_cu * p->cus;
     const bool eft = p->mode == SPHINT_EFT_FP64;
     if (p->ppt == 1) eft ? launch_batch<1, 1>(p, (unsigned)grid, st) : launch_batch<0, 1>(p, (unsigned)grid, st);
@@ -309,12 +321,13 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
         if (!bar) continue;
         *bar = 0;
         if (key == line) {
-          int ppt = 0, wg = -1;
-          if (sscanf(bar + 1, "%d %d", &ppt, &wg) == 2 && (ppt >= 1 && ppt <= 4) &&
-              wg >= 0) {
+          int ppt = 0, wg = -1, lb = 0;
+          if (sscanf(bar + 1, "%d %d %d", &ppt, &wg, &lb) >= 2 && (ppt >= 1 && ppt <= 4) &&
+              wg >= 0 && (lb == 0 || lb == 1)) {
             fclose(f);
             p->ppt = ppt;
             p->wg_per_cu = wg;
+            p->lookback = lb == 1;
             return layout(p);
           }
         }
@@ -334,15 +347,18 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
   hipEvent_t e0 = ev.e0, e1 = ev.e1;
   float best = 1e30f;
   int best_ppt = 1, best_wg = 0;
+  bool best_lb = false;
   const int ppts[4] = {1, 2, 3, 4};
-  for (int pi = 0; pi < 4; ++pi) {
-    const int ppt = ppts[pi];
-    const int res = resident_per_cu(p, ppt);
+  for (int ci = 0; ci < 8; ++ci) {
+    const bool lb = ci >= 4;
+    const int ppt = ppts[ci & 3];
+    const int res = resident_per_cu(p, ppt, lb);
     const int wgs[4] = {res, res > 1 ? res - 1 : 1, res > 2 ? res / 2 : 1, 1};
     for (int wi = 0; wi < 4; ++wi) {
       if (wi > 0 && wgs[wi] == wgs[wi - 1]) continue;
       p->ppt = ppt;
       p->wg_per_cu = wgs[wi];
+      p->lookback = lb;
       sphint_status s = layout(p);
       if (s != SPHINT_OK) return s;
       if (enqueue(p, st) != SPHINT_OK) return SPHINT_E_HIP;  // warm-up
@@ -357,16 +373,18 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
         best = ms;
         best_ppt = ppt;
         best_wg = wgs[wi];
+        best_lb = lb;
       }
     }
   }
   p->ppt = best_ppt;
   p->wg_per_cu = best_wg;
+  p->lookback = best_lb;
   sphint_status s = layout(p);
   if (s == SPHINT_OK && cache_path) {
     FILE* f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "%s|%d %d\n", key.c_str(), best_ppt, best_wg);
+      fprintf(f, "%s|%d %d %d\n", key.c_str(), best_ppt, best_wg, best_lb ? 1 : 0);
       fclose(f);
     }
   }
@@ -388,6 +406,18 @@ extern "C" sphint_status sphint_batch_set_params(sphint_plan* p, int pairs_per_t
     return SPHINT_E_INVAL;
   p->ppt = pairs_per_thread;
   p->wg_per_cu = wg_per_cu;
+  return layout(p);
+}
+
+extern "C" sphint_status sphint_batch_scan(const sphint_plan* p, int* lookback) {
+  if (!p || !lookback) return SPHINT_E_INVAL;
+  *lookback = p->lookback ? 1 : 0;
+  return SPHINT_OK;
+}
+
+extern "C" sphint_status sphint_batch_set_scan(sphint_plan* p, int lookback) {
+  if (!p || (lookback != 0 && lookback != 1)) return SPHINT_E_INVAL;
+  p->lookback = lookback == 1;
   return layout(p);
 }
 
@@ -488,7 +518,7 @@ void launch_run(const KArgs* d_args, const int64_t* d_base, int n, int64_t total
   const int per_cu = max_resident<MODE, PPT, CSR>();
   int64_t grid = (total_tiles + 1 + NWAVE - 1) / NWAVE;  // + the scanner
   if ((int64_t)per_cu * device_cus() < grid) grid = (int64_t)per_cu * device_cus();
-  hipLaunchKernelGGL((k_batch<MODE, PPT, CSR>), dim3((unsigned)grid), dim3(BLOCK), 0, st, d_args,
+  hipLaunchKernelGGL((k_batch<MODE, PPT, CSR, false>), dim3((unsigned)grid), dim3(BLOCK), 0, st, d_args,
                      d_base, n, total_tiles);
 }
 

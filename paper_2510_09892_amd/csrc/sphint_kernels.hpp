@@ -105,6 +105,60 @@ __device__ __forceinline__ int64_t wait_prefix(uint64_t* status, int64_t tile, u
   return (int64_t)(w >> 2);
 }
 
+// Decoupled look-back, the scanner's alternative (tile order is prefix order; a tile's state
+// word goes 0 -> ST_AGG (its hit count) -> ST_INCL (its inclusive prefix)).  The exclusive
+// prefix of `tile` is read from its predecessors: lane l of a window reads tile pos - l
+// (tiles before 0 count as an inclusive prefix of 0); aggregates are summed up to the
+// nearest inclusive prefix, which ends the walk, else the window moves 64 tiles back.  A
+// window in which a tile before that point has not reported yet is read again (bounded
+// wait, as wait_prefix).  The tile's own inclusive prefix is then published.  Every tile
+// looked at belongs to a running wavefront that publishes its count without waiting for a
+// later tile, so the walk ends.
+constexpr uint64_t ST_INCL = 3;
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int64_t lookback_prefix(uint64_t* status, int64_t tile, int agg,
+                                                   uint32_t* ws) {
+  const int lane = __lane_id();
+  int64_t excl = 0;
+  int64_t pos = tile - 1;
+  uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  unsigned polls = 0;
+  while (pos >= 0) {  // wavefront-uniform
+    const int64_t j = pos - lane;
+    const uint64_t w = j >= 0 ? __hip_atomic_load(status + j, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT)
+                              : ST_INCL;
+    const unsigned st = (unsigned)(w & 3u);
+    const unsigned long long incl = __ballot(st == ST_INCL);
+    const int stop = incl ? __ffsll(incl) - 1 : 64;  // nearest inclusive prefix, if any
+    const unsigned long long upto = stop >= 63 ? ~0ull : ((1ull << (stop + 1)) - 1);
+    if (__ballot(st == 0u) & upto) {  // a tile before it has not reported yet
+      bool quit = false;
+      if (lane == 0) quit = wait_expired(t0, polls, ws);
+      if (__shfl((int)quit, 0, 64)) {
+        excl = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    excl += wave_sum(lane <= stop ? (int64_t)(w >> 2) : 0);
+    if (stop < 64) break;
+    pos -= 64;
+    t0 = __builtin_amdgcn_s_memrealtime();
+  }
+  if (lane == 0)
+    __hip_atomic_store(status + tile, ((uint64_t)(excl + agg) << 2) | ST_INCL, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
 // The scanner (one whole wavefront) for tiles [0, ntiles) of one call: publishes each tile's
 // exclusive prefix in place of its aggregate and finally the call's total.  A pass reads
 // K * 64 consecutive tile states with contiguous 512-byte loads, transposes them through
@@ -438,6 +492,16 @@ __device__ __forceinline__ void flush_tile(const KArgs& a, int64_t tile, int cou
   __builtin_amdgcn_wave_barrier();
 }
 
+// The exclusive prefix of a finished tile: published by the scanner (LB == false), or found
+// by decoupled look-back (LB == true; the owner of a call's last tile then writes its total).
+template <bool LB>
+__device__ __forceinline__ int64_t tile_prefix(const KArgs& a, int64_t tile, int agg) {
+  if (!LB) return wait_prefix(a.status, tile, a.ws);
+  const int64_t prefix = lookback_prefix(a.status, tile, agg, a.ws);
+  if (tile == a.ntiles - 1 && __lane_id() == 0) *a.ototal = prefix + agg;
+  return prefix;
+}
+
 // One wavefront's share of the tiles: tiles come from `next` (the KArgs index and local
 // tile, or false when done).  Loads run one row ahead of evaluation (the next tile's first
 // row is fetched while the current tile's last row is evaluated).  A tile's hit count is
@@ -445,7 +509,7 @@ __device__ __forceinline__ void flush_tile(const KArgs& a, int64_t tile, int cou
 // first FLUSH_AT rows of the next tile, which gives the scanner that much time to publish
 // its offset.  Rows evaluated after that point go straight to the staging buffer, so at most
 // FLUSH_AT rows of results are held in registers.
-template <int MODE, int WPPT, bool CSR, int FLUSH_AT, class Next>
+template <int MODE, int WPPT, bool CSR, int FLUSH_AT, bool LB, class Next>
 __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT, CSR>& sh,
                                           Next&& next) {
   static_assert(FLUSH_AT >= 1 && FLUSH_AT <= WPPT, "flush point inside the tile");
@@ -485,7 +549,7 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
       if (j + 1 == FLUSH_AT) {
         if (pending) {
           const KArgs& pa = args[pm];
-          const int64_t prefix = wait_prefix(pa.status, ptile, pa.ws);
+          const int64_t prefix = tile_prefix<LB>(pa, ptile, pagg);
           flush_tile<WPPT>(pa, ptile, pagg, prefix, st);
         }
 #pragma unroll
@@ -511,7 +575,7 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
   }
   if (pending) {
     const KArgs& pa = args[pm];
-    const int64_t prefix = wait_prefix(pa.status, ptile, pa.ws);
+    const int64_t prefix = tile_prefix<LB>(pa, ptile, pagg);
     flush_tile<WPPT>(pa, ptile, pagg, prefix, st);
   }
 }
@@ -543,7 +607,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     return;
   }
   int64_t t = gw;
-  wave_loop<MODE, WPPT, CSR, flush_at<MODE, WPPT>()>(&a, sh, [&](int& m, int64_t& tile) {
+  wave_loop<MODE, WPPT, CSR, flush_at<MODE, WPPT>(), false>(&a, sh, [&](int& m, int64_t& tile) {
     if (t >= a.ntiles) return false;
     m = 0;
     tile = t;

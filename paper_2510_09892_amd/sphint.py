@@ -33,6 +33,7 @@ EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_batch_plan_create", "sphint_batch_autotune", "sphint_batch_launch",
            "sphint_batch_params", "sphint_batch_set_params", "sphint_batch_check",
            "sphint_plan_destroy", "sphint_batch_run_workspace_size", "sphint_batch_run",
+           "sphint_batch_scan", "sphint_batch_set_scan",
            "sphint_candidates_workspace_size", "sphint_candidates_count",
            "sphint_candidates_fill",
            "sphint_arc_arc",
@@ -104,6 +105,10 @@ def load():
     lib.sphint_batch_params.restype = ctypes.c_int
     lib.sphint_batch_set_params.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.sphint_batch_set_params.restype = ctypes.c_int
+    lib.sphint_batch_scan.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.sphint_batch_scan.restype = ctypes.c_int
+    lib.sphint_batch_set_scan.argtypes = [vp, ctypes.c_int]
+    lib.sphint_batch_set_scan.restype = ctypes.c_int
     lib.sphint_batch_check.argtypes = [vp]
     lib.sphint_batch_check.restype = ctypes.c_int
     lib.sphint_candidates_workspace_size.argtypes = [i64]
@@ -615,6 +620,15 @@ class BatchPlan:
     def set_params(self, pairs_per_thread, wg_per_cu):
         _check(load().sphint_batch_set_params(self.handle, pairs_per_thread, wg_per_cu),
                "sphint_batch_set_params")
+
+    def lookback(self):
+        """True when tile offsets come from decoupled look-back, False for the scanner."""
+        v = ctypes.c_int()
+        _check(load().sphint_batch_scan(self.handle, ctypes.byref(v)), "sphint_batch_scan")
+        return bool(v.value)
+
+    def set_lookback(self, on):
+        _check(load().sphint_batch_set_scan(self.handle, 1 if on else 0), "sphint_batch_set_scan")
 
     def check(self):
         """Synchronises; raises if a kernel of the last launch reported an internal limit or

@@ -2,7 +2,8 @@
 
 * One graph-replayed launch over all meshes gives, for every mesh, the bytes of a
   per-mesh sphint_arc_constlat call (counts, flags, hits), in both modes.
-* Every tile/schedule parameter choice the autotuner may pick gives the same bytes.
+* Every tile/schedule parameter choice the autotuner may pick (pairs per lane, workgroups
+  per CU, scanner or decoupled look-back) gives the same bytes.
 * Graph replays, with eager work and synchronisations between them, all give the same
   bytes; the autotuner's cache file is written and read back.
 * One small mesh against the oracle.
@@ -105,25 +106,29 @@ def test_batch_equals_per_mesh(torch_cuda, mode, tmp_path):
     ref = per_mesh(torch, devs, mode)
     plan = sphint.BatchPlan(devs, mode=mode)
     try:
-        for ppt in (1, 2, 3, 4):
-            for wg in (0, 1, 2):
-                note(f"{mode}: params ppt={ppt} wg_per_cu={wg}")
-                plan.set_params(ppt, wg)
-                scrub(torch, devs)
-                plan.launch()
-                torch.cuda.synchronize()
-                plan.check()
-                for d, r in zip(devs, ref):
-                    assert same(read(d["out"]), r), (ppt, wg)
+        for lb in (False, True):
+            plan.set_lookback(lb)
+            assert plan.lookback() == lb
+            for ppt in (1, 2, 3, 4):
+                for wg in (0, 1, 2):
+                    note(f"{mode}: params ppt={ppt} wg_per_cu={wg} lookback={lb}")
+                    plan.set_params(ppt, wg)
+                    scrub(torch, devs)
+                    plan.launch()
+                    torch.cuda.synchronize()
+                    plan.check()
+                    for d, r in zip(devs, ref):
+                        assert same(read(d["out"]), r), (ppt, wg, lb)
         cache = os.path.join(str(tmp_path), "tune.txt")
         note(f"{mode}: autotune")
         plan.autotune(cache)
-        chosen = plan.params()
-        assert chosen[0] in (1, 2, 3, 4) and chosen[1] >= 0
+        chosen = plan.params(), plan.lookback()
+        assert chosen[0][0] in (1, 2, 3, 4) and chosen[0][1] >= 0
         assert os.path.exists(cache) and open(cache).read().strip()
         plan.set_params(1, 1)
+        plan.set_lookback(not chosen[1])
         plan.autotune(cache)  # read back from the cache
-        assert plan.params() == chosen
+        assert (plan.params(), plan.lookback()) == chosen
         for rep in range(4):  # graph replays with eager work in between
             note(f"{mode}: replay {rep}")
             scrub(torch, devs)

@@ -58,7 +58,7 @@ def test_full_batch_equals_per_mesh_and_sampled_oracle(torch_cuda, meshes, mode)
     plan = sphint.BatchPlan(meshes, mode=mode)
     try:
         plan.autotune()
-        note(f"{mode}: autotuned params {plan.params()}")
+        note(f"{mode}: autotuned params {plan.params()}, look-back {plan.lookback()}")
         plan.launch()
         torch.cuda.synchronize()
         plan.check()
