@@ -1,17 +1,27 @@
 """Serving loop for arc x constant-latitude intersection requests on one GPU.
 
 Each request is one mesh: arcs (binary64 SoA endpoints), a latitude table and CSR
-candidate lists.  Requests arrive over time.  One is admitted when a slot is free and its
-device footprint (inputs + CSR + 2 nnz hit slots + counts, flags and workspace) fits the
-device-memory budget; its inputs go from pinned host memory into the slot's device arena
-with one copy on the slot's stream, and the library call is enqueued behind that copy.
-Slots run on separate streams, so a request's copy overlaps other requests' kernels, and
-requests that arrive while others are on the device are admitted as soon as a slot and
-memory are free (continuous batching; the library itself orders its kernel launches on the
-device, whose grids each cover the whole device).  A slot's arena is kept for later
-requests and grows (within the budget) only when a request does not fit.
+candidate lists.  Requests arrive over time and are served by continuous batching:
 
-Latency runs from a request's arrival to the completion of its kernel on the device
+* admission: a request is admitted when one of the request slots is free and its device
+  arena (inputs, CSR lists, 2 nnz hit slots, counts and flags) fits the device-memory
+  budget together with the other arenas and the launch workspace; its inputs then go from
+  pinned host memory into the arena with one copy, on the copy stream with the fewest bytes
+  outstanding (several copy streams, so a small request's copy does not queue behind a large
+  one's);
+* batching: admitted requests whose copy has finished wait for the next launch; a launch
+  takes up to SPHINT_BATCH_RUN_MAX of them (and at most a set number of pairs) and runs them
+  in ONE
+  persistent kernel (sphint_batch_run), whose tiles cover all its requests, so the work
+  of co-resident requests shares the device instead of queueing whole-device launches;
+* pipelining: up to `depth` launches are enqueued at once on the compute stream, so a
+  launch formed from the requests that arrived during the previous one is already queued
+  behind it when it ends;
+* completion: after each launch the kernels' error word and every request's hit total are
+  copied to pinned host memory; the loop checks both for every request when the launch has
+  finished, records latencies and frees the slots.
+
+Latency runs from a request's arrival to the completion of its launch on the device
 (device timestamps mapped onto the host clock through one reference event), reported with
 and without the request's own host-to-device copy time.
 
@@ -35,7 +45,7 @@ def _align(n):
 
 
 class Payload:
-    """One request's inputs packed into one pinned host buffer, and its device layout."""
+    """One request's inputs packed into one pinned host buffer, and its arena layout."""
 
     def __init__(self, mesh: inputs.CsrMesh):
         import torch
@@ -56,35 +66,60 @@ class Payload:
         # outputs after the inputs
         cap = 2 * self.nnz
         self.capacity = cap
-        sizes = dict(count=self.nnz, flags=self.nnz, total=8, x=8 * cap, y=8 * cap,
-                     pair=8 * cap, root=cap, ws=sphint.workspace_size(self.nnz))
+        sizes = dict(count=self.nnz, flags=self.nnz, x=8 * cap, y=8 * cap, pair=8 * cap, root=cap)
         self.out_offs = {}
         for k, b in sizes.items():
             self.out_offs[k] = o
             o = _align(o + b)
         self.footprint = o
-        self.ws_bytes = sizes["ws"]
 
-    def launch(self, base, mode, stream):
-        """Enqueues the library call on the arena at device address ``base``."""
+    def desc(self, base, total_addr):
+        """The request's sphint_mesh_desc on the arena at device address ``base``, with its
+        hit total written to ``total_addr``."""
         a = [base + off for off in self.in_offs]
         o = {k: base + v for k, v in self.out_offs.items()}
-        sphint.arc_constlat_raw(
-            self.n_arcs, (a[0], a[1], a[2]), (a[3], a[4], a[5]), a[6], self.n_lat, a[7], a[8],
-            self.nnz, (o["x"], o["y"], o["pair"], o["root"], self.capacity), o["count"],
-            o["flags"], o["total"], mode, o["ws"], self.ws_bytes, stream)
+        return sphint.MeshDesc(
+            self.n_arcs, self.n_lat, self.nnz, sphint.PtsSoA(a[0], a[1], a[2]),
+            sphint.PtsSoA(a[3], a[4], a[5]), a[6], a[7], a[8],
+            sphint.Hits(o["x"], o["y"], o["pair"], o["root"], self.capacity), o["count"],
+            o["flags"], total_addr)
 
 
 class _Slot:
-    def __init__(self, torch, device):
-        self.stream = torch.cuda.Stream(device=device)  # default priority
+    """A request's device arena (kept for later requests) and its copy events."""
+
+    def __init__(self, torch):
         self.arena = None
         self.capacity = 0
         self.rid = None
         self.payload = None
+        self.t_admit = 0.0
+        self.copy_k = 0
+        self.copied = False
         self.ev_h2d0 = torch.cuda.Event(enable_timing=True)
         self.ev_h2d1 = torch.cuda.Event(enable_timing=True)
+
+
+class _Launch:
+    """One batched launch in flight: its requests, events and result buffers."""
+
+    def __init__(self, torch, device):
+        n = sphint.BATCH_RUN_MAX
+        self.totals = torch.zeros(n + 1, dtype=torch.int64, device=device)  # [0]: error word
+        self.host = torch.zeros(n + 1, dtype=torch.int64, pin_memory=True)
         self.ev_done = torch.cuda.Event(enable_timing=True)
+        self.ev_read = torch.cuda.Event()
+        self.slots = []
+        self.seq = -1
+
+
+def _small_half(lat, sizes):
+    """p50/p99 latency (ms) of the requests with at most the median number of pairs."""
+    if not lat:
+        return None
+    lat, sizes = np.asarray(lat), np.asarray(sizes)
+    sel = lat[sizes <= np.median(sizes)]
+    return {"p50": 1e3 * _pct(sel, 50), "p99": 1e3 * _pct(sel, 99)}
 
 
 def _pct(v, q):
@@ -94,23 +129,48 @@ def _pct(v, q):
 
 
 class Server:
-    """Admission by device-memory budget, one stream per slot, latency accounting."""
+    """Continuous batching: admission by device-memory budget, up to `max_batch` requests
+    per persistent launch, `depth` launches in flight, latency accounting."""
 
-    def __init__(self, mode="eft", budget_bytes=64 << 30, slots=8, device="cuda"):
+    def __init__(self, mode="eft", budget_bytes=64 << 30, slots=32, max_batch=None, depth=2,
+                 max_launch_pairs=1 << 25, copy_streams=4, device="cuda"):
         import torch
         self.torch = torch
         self.mode = mode
         self.budget = int(budget_bytes)
         self.device = torch.device(device)
-        self.slots = [_Slot(torch, self.device) for _ in range(slots)]
-        self.reserved = 0  # bytes held by slot arenas
+        self.slots = [_Slot(torch) for _ in range(slots)]
+        self.max_batch = min(max_batch or sphint.BATCH_RUN_MAX, sphint.BATCH_RUN_MAX)
+        self.depth = depth
+        self.max_launch_pairs = int(max_launch_pairs)
+        # default priority for every stream
+        self.copy_streams = [torch.cuda.Stream(device=self.device) for _ in range(copy_streams)]
+        self.copy_pending = [0] * copy_streams  # bytes of admitted, unfinished copies
+        self.compute_stream = torch.cuda.Stream(device=self.device)
+        self.read_stream = torch.cuda.Stream(device=self.device)
+        self.launches = [_Launch(torch, self.device) for _ in range(depth)]
+        self.ws = None
+        self.ws_pairs = -1
+        self.reserved = 0  # bytes held by slot arenas and the launch workspace
+
+    # -- launch workspace: sized once per run for the largest launch the loop forms
+    def _workspace(self, pairs):
+        if pairs > self.ws_pairs:
+            if self.ws is not None:
+                self.reserved -= self.ws.numel()
+            self.torch.cuda.synchronize(self.device)
+            self.ws = None
+            need = sphint.batch_run_workspace_size(sphint.BATCH_RUN_MAX, pairs)
+            self.ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+            self.ws_pairs = pairs
+            self.reserved += need
+        return self.ws
 
     # -- arena management (only free slots are touched: nothing of theirs is in flight)
     def _fit(self, free, need):
         """A free slot whose arena holds `need` bytes, growing one within the budget if
         necessary (releasing idle arenas of other free slots first); None if none can.
-        The budget bounds the bytes the slots' arenas hold; memory of a released arena
-        stays in PyTorch's cache and serves the next arena."""
+        Memory of a released arena stays in PyTorch's cache and serves the next arena."""
         ok = [s for s in free if s.capacity >= need]
         if ok:
             return min(ok, key=lambda s: s.capacity)
@@ -125,32 +185,51 @@ class Server:
                 return None
         self.reserved -= s.capacity
         s.arena = None
-        # allocated on the device's default stream, so that a released arena's memory is
-        # reusable by every slot (only idle slots' arenas are ever released or replaced)
+        # allocated on the device's default stream: a released arena's memory is reusable
+        # by every slot (only idle slots' arenas are ever released or replaced)
         s.arena = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
         s.capacity = need
         self.reserved += need
         return s
 
-    def _issue(self, s, rid, p):
+    def _admit(self, s, rid, p):
         s.rid, s.payload = rid, p
-        base = s.arena.data_ptr()
-        with self.torch.cuda.stream(s.stream):
-            s.ev_h2d0.record(s.stream)
+        k = min(range(len(self.copy_streams)), key=lambda i: self.copy_pending[i])
+        cs = self.copy_streams[k]
+        s.copy_k = k
+        self.copy_pending[k] += p.in_bytes
+        with self.torch.cuda.stream(cs):
+            s.ev_h2d0.record(cs)
             s.arena[:p.in_bytes].copy_(p.host, non_blocking=True)
-            s.ev_h2d1.record(s.stream)
-            p.launch(base, self.mode, s.stream.cuda_stream)
-            s.ev_done.record(s.stream)
+            s.ev_h2d1.record(cs)
 
-    def _collect(self, s):
-        """Outputs of a finished slot as host arrays (counts, flags, hits)."""
+    def _launch(self, L, group):
+        """Enqueues one batched launch over the slots in `group` on the compute stream."""
+        torch = self.torch
+        cs = self.compute_stream
+        L.slots = group
+        tot = L.totals.data_ptr()
+        descs = (sphint.MeshDesc * len(group))()
+        for i, s in enumerate(group):
+            cs.wait_event(s.ev_h2d1)  # already complete (the loop checked): orders the streams
+            descs[i] = s.payload.desc(s.arena.data_ptr(), tot + 8 * (i + 1))
+        ws = self.ws
+        sphint.batch_run_raw(descs, len(group), self.mode, ws.data_ptr(), ws.numel(),
+                             cs.cuda_stream)
+        with torch.cuda.stream(cs):
+            L.ev_done.record(cs)
+            # the error word (header word 1) and the hit totals, for every request
+            L.totals[0:1].copy_(ws[:8].view(torch.int64), non_blocking=True)
+            L.host[:len(group) + 1].copy_(L.totals[:len(group) + 1], non_blocking=True)
+            L.ev_read.record(cs)
+
+    def _collect(self, s, total):
+        """Outputs of a finished request as host arrays (counts, flags, hits)."""
         p = s.payload
         a = s.arena
-        with self.torch.cuda.stream(s.stream):
-            o = p.out_offs
-            total = int(a[o["total"]:o["total"] + 8].view(self.torch.int64).cpu()[0])
-            sphint.check_raw(a.data_ptr() + o["ws"], total, p.capacity)
-            k = total
+        o = p.out_offs
+        k = total
+        with self.torch.cuda.stream(self.read_stream):
             res = dict(total=total,
                        count=a[o["count"]:o["count"] + p.nnz].cpu().numpy(),
                        flags=a[o["flags"]:o["flags"] + p.nnz].cpu().numpy(),
@@ -160,18 +239,27 @@ class Server:
                        root=a[o["root"]:o["root"] + k].cpu().numpy())
         return res
 
-    def run(self, arrivals, payload_of, keep_outputs=False, check_every=0):
+    def run(self, arrivals, payload_of, keep_outputs=False):
         """Serves requests i = 0..len(arrivals)-1 arriving at ``arrivals[i]`` seconds after
         the start; ``payload_of(i)`` gives request i's Payload.  Returns a report dict (and
         the outputs by request id when ``keep_outputs``: True keeps every request's, a
-        callable keeps those of the ids it accepts).  ``check_every`` = k > 0 also reads back
-        the hit total and error word of every k-th request."""
+        callable keeps those of the ids it accepts; each with its launch's sequence number
+        and size, and its admission and completion times).  Every request's hit total and
+        the error word of its launch are checked."""
         torch = self.torch
         keep = keep_outputs if callable(keep_outputs) else (lambda rid: bool(keep_outputs))
         n = len(arrivals)
+        biggest = 0
         for p in {id(payload_of(i)): payload_of(i) for i in range(n)}.values():
+            biggest = max(biggest, p.nnz)
             if p.footprint > self.budget:
                 raise sphint.SphintError(f"a request needs {p.footprint} bytes, over the budget")
+        # pairs per launch: at most max_launch_pairs, and a workspace of at most a sixteenth
+        # of the budget (about 4 bytes per pair), but always room for the largest request
+        cap_pairs = max(biggest, min(self.max_launch_pairs, self.budget // 16 // 5))
+        self._workspace(cap_pairs)
+        if self.reserved > self.budget:
+            raise sphint.SphintError("the launch workspace alone exceeds the budget")
         torch.cuda.synchronize(self.device)
         ev_ref = torch.cuda.Event(enable_timing=True)
         tb = time.perf_counter()
@@ -179,40 +267,60 @@ class Server:
         ev_ref.synchronize()
         t_ref = (tb + time.perf_counter()) / 2
         t0 = time.perf_counter()
-        queue = collections.deque()
-        nxt = 0
-        done = 0
-        lat, lat_nocopy, h2d = [], [], []
+        queue = collections.deque()   # arrived, not admitted
+        copying = []                  # admitted, copy in flight
+        ready = collections.deque()   # inputs on the device, not launched
+        inflight = collections.deque()
+        idle_launches = list(self.launches)
+        nxt = done = 0
+        lat, lat_nocopy, h2d, sizes = [], [], [], []
         pairs = hits = 0
         outputs = {}
-        busy = []
+        busy = set()
         blocked = 0
-        max_inflight = 0
+        n_launch = 0
+        per_launch = []
+        shared = 0
+        max_resident = 0
         while done < n:
             now = time.perf_counter() - t0
             progressed = False
             while nxt < n and arrivals[nxt] <= now:
                 queue.append(nxt)
                 nxt += 1
-            for s in list(busy):
-                if s.ev_done.query():
-                    busy.remove(s)
+            # completions, in launch order
+            while inflight and inflight[0].ev_read.query():
+                L = inflight.popleft()
+                vals = L.host[:len(L.slots) + 1].numpy()
+                err = (int(vals[0]) >> 32) & 0xffffffff  # header word 1: the error bits
+                if err:
+                    raise sphint.SphintError(f"launch reported device error bits {err:#x}")
+                t_done = t_ref + ev_ref.elapsed_time(L.ev_done) / 1e3 - t0
+                for i, s in enumerate(L.slots):
                     p, rid = s.payload, s.rid
-                    t_done = t_ref + ev_ref.elapsed_time(s.ev_done) / 1e3 - t0
+                    total = int(vals[i + 1])
+                    if total > p.capacity:
+                        raise sphint.SphintError(f"request {rid}: {total} hits over capacity")
                     c = s.ev_h2d0.elapsed_time(s.ev_h2d1) / 1e3
                     lat.append(t_done - arrivals[rid])
+                    sizes.append(p.nnz)
                     lat_nocopy.append(t_done - arrivals[rid] - c)
                     h2d.append(c)
                     pairs += p.nnz
-                    kept = keep(rid)
-                    if kept or (check_every and rid % check_every == 0):
-                        r = self._collect(s)
-                        hits += r["total"]
-                        if kept:
-                            outputs[rid] = r
+                    hits += total
+                    if keep(rid):
+                        outputs[rid] = self._collect(s, total)
+                        outputs[rid].update(launch=L.seq, launch_size=len(L.slots),
+                                            t_admit=s.t_admit, t_done=t_done)
                     s.rid = s.payload = None
+                    busy.discard(s)
                     done += 1
-                    progressed = True
+                if len(L.slots) > 1:
+                    shared += len(L.slots)
+                L.slots = []
+                idle_launches.append(L)
+                progressed = True
+            # admissions
             free = [s for s in self.slots if s not in busy]
             while queue and free:
                 rid = queue[0]
@@ -223,32 +331,61 @@ class Server:
                     break
                 queue.popleft()
                 free.remove(s)
-                self._issue(s, rid, p)
-                busy.append(s)
+                busy.add(s)
+                s.t_admit = time.perf_counter() - t0
+                self._admit(s, rid, p)
+                copying.append(s)
                 progressed = True
-            max_inflight = max(max_inflight, len(busy))
+            max_resident = max(max_resident, len(busy))
+            # copies that have finished: those requests can join a launch
+            for s in list(copying):
+                if s.ev_h2d1.query():
+                    copying.remove(s)
+                    self.copy_pending[s.copy_k] -= s.payload.in_bytes
+                    ready.append(s)
+                    progressed = True
+            # launches: every request whose inputs are on the device joins the next launch
+            while ready and idle_launches:
+                group = [ready.popleft()]
+                npairs = group[0].payload.nnz
+                while (ready and len(group) < self.max_batch
+                       and npairs + ready[0].payload.nnz <= cap_pairs):
+                    npairs += ready[0].payload.nnz
+                    group.append(ready.popleft())
+                L = idle_launches.pop()
+                L.seq = n_launch
+                self._launch(L, group)
+                inflight.append(L)
+                n_launch += 1
+                per_launch.append(len(group))
+                progressed = True
             if not progressed:
                 time.sleep(0)
         torch.cuda.synchronize(self.device)
         wall = time.perf_counter() - t0
         rep = dict(requests=n, wall_s=wall, req_per_s=n / wall, pairs=pairs,
-                   pairs_per_s=pairs / wall,
+                   pairs_per_s=pairs / wall, hits=hits,
                    latency_ms={"p50": 1e3 * _pct(lat, 50), "p99": 1e3 * _pct(lat, 99),
                                "max": 1e3 * max(lat)},
                    latency_without_h2d_ms={"p50": 1e3 * _pct(lat_nocopy, 50),
                                            "p99": 1e3 * _pct(lat_nocopy, 99)},
                    h2d_ms={"p50": 1e3 * _pct(h2d, 50), "p99": 1e3 * _pct(h2d, 99)},
-                   slots=len(self.slots), max_inflight=max_inflight,
-                   budget_bytes=self.budget, reserved_bytes=self.reserved,
-                   admission_waits_on_budget=blocked, mode=self.mode)
-        if keep_outputs or check_every:
-            rep["hits_checked"] = hits
+                   latency_smaller_half_ms=_small_half(lat, sizes),
+                   launches=n_launch, requests_per_launch_mean=n / max(n_launch, 1),
+                   requests_per_launch_max=max(per_launch) if per_launch else 0,
+                   shared_launch_frac=shared / n, max_resident_requests=max_resident,
+                   slots=len(self.slots), depth=self.depth, max_batch=self.max_batch,
+                   launch_pairs_cap=cap_pairs, budget_bytes=self.budget,
+                   reserved_bytes=self.reserved, admission_waits_on_budget=blocked,
+                   requests_checked=done, mode=self.mode)
         return (rep, outputs) if keep_outputs else rep
 
     def close(self):
         for s in self.slots:
             s.arena = None
             s.capacity = 0
+        self.ws = None
+        self.ws_pairs = -1
         self.reserved = 0
 
 

@@ -1,12 +1,15 @@
-"""GPU: the serving loop and launches from several streams.
+"""GPU: the serving loop (continuous batching) and launches from several streams.
 
-* Every request's outputs in a served mix (several slots in flight, admission held back
-  by a small device-memory budget) are bit-identical to the same request run alone.
+* Every request's outputs in a served mix (several requests merged into each persistent
+  launch, admission held back by a small device-memory budget) are bit-identical to the
+  same request run alone.
+* Small requests arriving while a large one is resident are admitted at once, merged into
+  shared persistent launches and finish before it; their outputs equal their single calls.
 * Launches on different streams at once give the results of the same launches run one
   after the other (the library orders its launches on the device).
 * A few served requests are checked against the oracle.
 * At the serving configuration's own rate (Poisson, 2000 requests/s, requests of
-  log-uniform 1e3..1e6 arcs x 1..1000 latitudes, 64 GiB budget, 8 slots), a sample of the
+  log-uniform 1e3..1e6 arcs x 1..1000 latitudes, 64 GiB budget, 32 slots), a sample of the
   served requests equals the same requests run alone.
 """
 
@@ -76,10 +79,12 @@ def test_served_mix_equals_alone(torch_cuda, mode):
     note(f"serving {n_req} requests, budget {budget} bytes, 4 slots")
     rep, outs = srv.run(arrivals, lambda i: pool[which[i]], keep_outputs=True)
     srv.close()
-    note(f"served: {rep['req_per_s']:.0f} req/s, max in flight {rep['max_inflight']}, "
-         f"budget waits {rep['admission_waits_on_budget']}")
+    note(f"served: {rep['req_per_s']:.0f} req/s, {rep['launches']} launches, up to "
+         f"{rep['requests_per_launch_max']} requests each, budget waits "
+         f"{rep['admission_waits_on_budget']}")
     assert rep["requests"] == n_req and len(outs) == n_req
-    assert rep["max_inflight"] > 1
+    assert rep["max_resident_requests"] > 1
+    assert rep["requests_per_launch_max"] > 1 and rep["launches"] < n_req
     assert rep["admission_waits_on_budget"] > 0
     ref = {}
     for rid in range(n_req):
@@ -136,7 +141,7 @@ def test_full_rate_stream_sampled_equals_alone(torch_cuda, mode):
     meshes = [inputs.random_mesh(inputs.rng(4, seed), n_arcs, n_lat) for n_arcs, n_lat, seed in specs]
     pool = [serve.Payload(m) for m in meshes]
     arrivals, _ = inputs.request_stream(rate_hz=2000.0, duration_s=2.0, seed_tag=4)
-    srv = serve.Server(mode=mode, budget_bytes=64 << 30, slots=8)
+    srv = serve.Server(mode=mode, budget_bytes=64 << 30, slots=32)
     note(f"serving {len(arrivals)} requests at 2000/s")
     rep, outs = srv.run(arrivals, lambda i: pool[i % len(pool)],
                         keep_outputs=lambda rid: rid % 53 == 0)
@@ -150,3 +155,34 @@ def test_full_rate_stream_sampled_equals_alone(torch_cuda, mode):
         if k not in ref:
             ref[k] = alone(torch, meshes[k], mode)
         assert same_bytes(r, ref[k]), (rid, k)
+
+
+def test_small_requests_behind_a_large_one(torch_cuda):
+    """A large request arrives first; small requests arriving while it is resident (its
+    inputs still being copied) are admitted at once, copied on other copy streams, merged
+    into shared persistent launches and finished before it (no head-of-line blocking);
+    every output equals its request's single call."""
+    from paper_2510_09892_amd import serve
+    torch = torch_cuda
+    large = inputs.random_mesh(inputs.rng(35, 1), 2_000_000, 1800)
+    smalls = [inputs.random_mesh(inputs.rng(35, 2 + k), 2000 + 700 * k, 20 + 5 * k)
+              for k in range(6)]
+    meshes = [large] + smalls
+    pool = [serve.Payload(m) for m in meshes]
+    note(f"large request: {large.nnz} pairs; small: {[m.nnz for m in smalls]}")
+    arrivals = np.array([0.0] + [2e-4 + 1e-5 * k for k in range(len(smalls))])
+    srv = serve.Server(mode="eft", budget_bytes=16 << 30, slots=16)
+    srv.run(arrivals * 0.0, lambda i: pool[i])  # warm-up: arenas, code
+    rep, outs = srv.run(arrivals, lambda i: pool[i], keep_outputs=True)
+    srv.close()
+    big = outs[0]
+    note(f"large: launch {big['launch']}, done at {1e3 * big['t_done']:.3f} ms; small: "
+         + ", ".join(f"launch {outs[i]['launch']} (size {outs[i]['launch_size']}, admitted "
+                     f"{1e3 * outs[i]['t_admit']:.3f}, done {1e3 * outs[i]['t_done']:.3f} ms)"
+                     for i in range(1, len(pool))))
+    for i in range(1, len(pool)):
+        assert outs[i]["t_admit"] < big["t_done"], i   # admitted while the large one ran
+        assert outs[i]["t_done"] < big["t_done"], i    # and not queued behind it
+    assert max(outs[i]["launch_size"] for i in range(1, len(pool))) > 1  # merged launches
+    for i, m in enumerate(meshes):
+        assert same_bytes(outs[i], alone(torch, m, "eft")), i
