@@ -6,9 +6,10 @@ candidate lists.  Requests arrive over time and are served by continuous batchin
 * admission: a request is admitted when one of the request slots is free and its device
   arena (inputs, CSR lists, 2 nnz hit slots, counts and flags) fits the device-memory
   budget together with the other arenas and the launch workspace; its inputs then go from
-  pinned host memory into the arena with one copy, on the copy stream with the fewest bytes
-  outstanding (several copy streams, so a small request's copy does not queue behind a large
-  one's);
+  pinned host memory into the arena in 4 MiB chunks on the copy stream, the loop keeping only a
+  few chunks in flight and always taking the next chunk from the request with the fewest
+  bytes left (so a small request's copy does not wait behind a large one's: the copy engine
+  serves one queue in order);
 * batching: admitted requests whose copy has finished wait for the next launch; a launch
   takes up to SPHINT_BATCH_RUN_MAX of them (and at most a set number of pairs) and runs them
   in ONE
@@ -94,8 +95,7 @@ class _Slot:
         self.rid = None
         self.payload = None
         self.t_admit = 0.0
-        self.copy_k = 0
-        self.copied = False
+        self.copy_off = 0
         self.ev_h2d0 = torch.cuda.Event(enable_timing=True)
         self.ev_h2d1 = torch.cuda.Event(enable_timing=True)
 
@@ -133,7 +133,8 @@ class Server:
     per persistent launch, `depth` launches in flight, latency accounting."""
 
     def __init__(self, mode="eft", budget_bytes=64 << 30, slots=32, max_batch=None, depth=2,
-                 max_launch_pairs=1 << 25, copy_streams=4, device="cuda"):
+                 max_launch_pairs=1 << 25, copy_chunk=1 << 22, copy_inflight=2 << 22,
+                 device="cuda"):
         import torch
         self.torch = torch
         self.mode = mode
@@ -144,8 +145,9 @@ class Server:
         self.depth = depth
         self.max_launch_pairs = int(max_launch_pairs)
         # default priority for every stream
-        self.copy_streams = [torch.cuda.Stream(device=self.device) for _ in range(copy_streams)]
-        self.copy_pending = [0] * copy_streams  # bytes of admitted, unfinished copies
+        self.copy_stream = torch.cuda.Stream(device=self.device)
+        self.copy_chunk = int(copy_chunk)        # bytes per copy
+        self.copy_inflight = int(copy_inflight)  # bytes of copies enqueued and not finished
         self.compute_stream = torch.cuda.Stream(device=self.device)
         self.read_stream = torch.cuda.Stream(device=self.device)
         self.launches = [_Launch(torch, self.device) for _ in range(depth)]
@@ -194,14 +196,26 @@ class Server:
 
     def _admit(self, s, rid, p):
         s.rid, s.payload = rid, p
-        k = min(range(len(self.copy_streams)), key=lambda i: self.copy_pending[i])
-        cs = self.copy_streams[k]
-        s.copy_k = k
-        self.copy_pending[k] += p.in_bytes
+        s.copy_off = 0
+
+    def _copy_chunk(self, s):
+        """Enqueues the next chunk of s's inputs; returns (event, bytes, last chunk?)."""
+        p = s.payload
+        cs = self.copy_stream
+        a, b = s.copy_off, min(s.copy_off + self.copy_chunk, p.in_bytes)
         with self.torch.cuda.stream(cs):
-            s.ev_h2d0.record(cs)
-            s.arena[:p.in_bytes].copy_(p.host, non_blocking=True)
-            s.ev_h2d1.record(cs)
+            if a == 0:
+                s.ev_h2d0.record(cs)
+            s.arena[a:b].copy_(p.host[a:b], non_blocking=True)
+            last = b == p.in_bytes
+            if last:
+                s.ev_h2d1.record(cs)
+                ev = s.ev_h2d1
+            else:
+                ev = self.torch.cuda.Event()
+                ev.record(cs)
+        s.copy_off = b
+        return ev, b - a, last
 
     def _launch(self, L, group):
         """Enqueues one batched launch over the slots in `group` on the compute stream."""
@@ -268,7 +282,9 @@ class Server:
         t_ref = (tb + time.perf_counter()) / 2
         t0 = time.perf_counter()
         queue = collections.deque()   # arrived, not admitted
-        copying = []                  # admitted, copy in flight
+        copying = []                  # admitted, inputs not all enqueued for copying
+        chunks = collections.deque()  # copies in flight: (event, bytes, slot, last chunk?)
+        chunk_bytes = 0
         ready = collections.deque()   # inputs on the device, not launched
         inflight = collections.deque()
         idle_launches = list(self.launches)
@@ -337,13 +353,22 @@ class Server:
                 copying.append(s)
                 progressed = True
             max_resident = max(max_resident, len(busy))
-            # copies that have finished: those requests can join a launch
-            for s in list(copying):
-                if s.ev_h2d1.query():
-                    copying.remove(s)
-                    self.copy_pending[s.copy_k] -= s.payload.in_bytes
+            # copies: finished chunks retire (a request whose last chunk finished can join a
+            # launch), then the queue is topped up from the request with the fewest bytes left
+            while chunks and chunks[0][0].query():
+                ev, nb, s, last = chunks.popleft()
+                chunk_bytes -= nb
+                if last:
                     ready.append(s)
-                    progressed = True
+                progressed = True
+            while copying and chunk_bytes < self.copy_inflight:
+                s = min(copying, key=lambda q: q.payload.in_bytes - q.copy_off)
+                ev, nb, last = self._copy_chunk(s)
+                chunks.append((ev, nb, s, last))
+                chunk_bytes += nb
+                if last:
+                    copying.remove(s)
+                progressed = True
             # launches: every request whose inputs are on the device joins the next launch
             while ready and idle_launches:
                 group = [ready.popleft()]
