@@ -170,6 +170,18 @@ sphint_status sphint_arc_constlat_noalloc(int64_t n_arcs, sphint_pts_soa p1, sph
                                           int32_t *out_error, sphint_mode mode, void *stream);
 
 /*
+ * Every wait inside a launch (a tile waiting for its output offset, the scanner waiting for
+ * a tile's count) is bounded: past the limit it gives up, the launch finishes with its
+ * outputs undefined, and sphint_check / sphint_batch_check report SPHINT_E_DEVICE.  This
+ * sets the limit, in seconds (default 2; 0 makes every wait give up at its first check),
+ * for calls enqueued afterwards from any thread (a batch plan takes the limit in force when
+ * it is created or its schedule is set, and keeps it in its graph).  A launch whose grid does not become
+ * resident in time (the device shared with other work) thus ends with an error instead of
+ * waiting forever.  SPHINT_E_INVAL for a negative, non-finite or over-3600 value.
+ */
+sphint_status sphint_set_wait_limit(double seconds);
+
+/*
  * Instrumentation.  While set (non-NULL), every sphint_arc_constlat call made from this host
  * thread records `start` (a hipEvent_t) on its stream immediately before its main kernel and
  * `stop` immediately after it, so the caller can time that kernel alone, and every

@@ -231,6 +231,12 @@ extern "C" sphint_status sphint_arc_constlat_noalloc(int64_t n_arcs, sphint_pts_
                          out_error);
 }
 
+extern "C" sphint_status sphint_set_wait_limit(double seconds) {
+  if (!(seconds >= 0.0 && seconds <= 3600.0)) return SPHINT_E_INVAL;
+  wait_ticks_setting().store((uint64_t)(seconds * 1e8), std::memory_order_relaxed);
+  return SPHINT_OK;
+}
+
 extern "C" sphint_status sphint_set_profile_events(void* start, void* stop) {
   if ((start == nullptr) != (stop == nullptr)) return SPHINT_E_INVAL;
   profile_events().start = (hipEvent_t)start;

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   if (!LB && gw == W) {  // the scanner follows the global tile order: mesh after mesh
     for (int m = 0; m < n_meshes; ++m) {
       const KArgs a = args[m];
-      scan_tiles<scan_k<PPT>()>(a.status, a.ntiles, a.ototal, a.ws,
+      scan_tiles<scan_k<PPT>()>(a.status, a.ntiles, a.ototal, a.ws, a.wait_ticks,
                                 reinterpret_cast<uint64_t*>(&sh.stage[wave]));
     }
     return;

@@ -107,6 +107,13 @@ inline sphint_status validate(int64_t n_arcs, const sphint_pts_soa& p1, const sp
   return SPHINT_OK;
 }
 
+// Limit of the kernels' bounded waits for launches enqueued from now on (real-time counter
+// ticks, 100 MHz); sphint_set_wait_limit sets it.
+inline std::atomic<uint64_t>& wait_ticks_setting() {
+  static std::atomic<uint64_t> ticks{WAIT_TICKS};
+  return ticks;
+}
+
 inline KArgs make_args(int64_t n_arcs, const sphint_pts_soa& p1, const sphint_pts_soa& p2,
                        const double* lat_z, int64_t n_lat, const int64_t* off,
                        const int32_t* idx, int64_t nnz, const sphint_hits& out,
@@ -129,6 +136,7 @@ inline KArgs make_args(int64_t n_arcs, const sphint_pts_soa& p1, const sphint_pt
   k.ws = ws;
   k.status = status;
   k.ntiles = ntiles;
+  k.wait_ticks = wait_ticks_setting().load(std::memory_order_relaxed);
   return k;
 }
 

@@ -21,9 +21,10 @@ constexpr int BLOCK = 256;
 constexpr int NWAVE = BLOCK / 64;
 constexpr size_t WS_HEADER = 256;  // counter + error word, padded
 constexpr uint64_t ST_AGG = 1, ST_PREFIX = 2;  // tile states (value << 2) | state
-// Bounded waits: a wait gives up after WAIT_TICKS of the 100 MHz real-time counter (2 s, far
-// beyond any real wait), sets ERR_SPIN, and every later wait of the launch gives up at once,
-// so a launch always ends (with the error reported by sphint_check).
+// Bounded waits: a wait gives up after KArgs::wait_ticks of the 100 MHz real-time counter
+// (by default WAIT_TICKS = 2 s, far beyond any real wait; sphint_set_wait_limit changes it),
+// sets ERR_SPIN, and every later wait of the launch gives up at once, so a launch always
+// ends (with the error reported by sphint_check).
 constexpr uint64_t WAIT_TICKS = 200000000ull;
 enum : uint32_t { ERR_SPIN = 1u, ERR_EXACT = 2u };
 
@@ -44,6 +45,7 @@ struct KArgs {
   uint32_t* ws;      // [0] tile counter, [1] error bits
   uint64_t* status;  // one word per tile: (value << 2) | state
   int64_t ntiles;
+  uint64_t wait_ticks;  // limit of every bounded wait (real-time counter ticks)
 };
 
 // The same pointer in the global address space: argument pointers read from memory (the
@@ -73,11 +75,12 @@ __device__ __forceinline__ void resolve_serial(bool need, F&& fn) {
 // whose predecessors have all reported; waiting wavefronts read only their own word.
 
 // True when this wait must give up (timed out, or another wait of the launch did).
-__device__ __forceinline__ bool wait_expired(uint64_t t0, unsigned& polls, uint32_t* ws) {
+__device__ __forceinline__ bool wait_expired(uint64_t t0, unsigned& polls, uint32_t* ws,
+                                             uint64_t ticks) {
   if ((++polls & 63u) == 0 &&
       (__hip_atomic_load(ws + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_SPIN))
     return true;
-  if (__builtin_amdgcn_s_memrealtime() - t0 > WAIT_TICKS) {
+  if (__builtin_amdgcn_s_memrealtime() - t0 >= ticks) {
     atomicOr(ws + 1, ERR_SPIN);
     return true;
   }
@@ -85,7 +88,8 @@ __device__ __forceinline__ bool wait_expired(uint64_t t0, unsigned& polls, uint3
 }
 
 // Waits (lane 0 polls, bounded) until the scanner has published the tile's exclusive prefix.
-__device__ __forceinline__ int64_t wait_prefix(uint64_t* status, int64_t tile, uint32_t* ws) {
+__device__ __forceinline__ int64_t wait_prefix(uint64_t* status, int64_t tile, uint32_t* ws,
+                                              uint64_t ticks) {
   const int lane = __lane_id();
   uint64_t w = 0;
   if (lane == 0) {
@@ -94,7 +98,7 @@ __device__ __forceinline__ int64_t wait_prefix(uint64_t* status, int64_t tile, u
     for (;;) {
       w = __hip_atomic_load(status + tile, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if ((w & 3u) == ST_PREFIX) break;
-      if (wait_expired(t0, polls, ws)) {
+      if (wait_expired(t0, polls, ws, ticks)) {
         w = 0;
         break;
       }
@@ -123,7 +127,7 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
 }
 
 __device__ __forceinline__ int64_t lookback_prefix(uint64_t* status, int64_t tile, int agg,
-                                                   uint32_t* ws) {
+                                                   uint32_t* ws, uint64_t ticks) {
   const int lane = __lane_id();
   int64_t excl = 0;
   int64_t pos = tile - 1;
@@ -140,7 +144,7 @@ __device__ __forceinline__ int64_t lookback_prefix(uint64_t* status, int64_t til
     const unsigned long long upto = stop >= 63 ? ~0ull : ((1ull << (stop + 1)) - 1);
     if (__ballot(st == 0u) & upto) {  // a tile before it has not reported yet
       bool quit = false;
-      if (lane == 0) quit = wait_expired(t0, polls, ws);
+      if (lane == 0) quit = wait_expired(t0, polls, ws, ticks);
       if (__shfl((int)quit, 0, 64)) {
         excl = 0;
         break;
@@ -178,7 +182,7 @@ __device__ __forceinline__ int64_t lane_scan(int64_t v) {  // inclusive scan ove
 
 template <int K>
 __device__ __forceinline__ void scan_tiles(uint64_t* status, int64_t ntiles, int64_t* ototal,
-                                           uint32_t* ws, uint64_t* lds) {
+                                           uint32_t* ws, uint64_t ticks, uint64_t* lds) {
   const int lane = __lane_id();
   constexpr int P = K + 1;  // padded row length of the transposed layout
   int64_t t = 0, run = 0;   // first tile without a prefix, hits before it
@@ -244,7 +248,7 @@ __device__ __forceinline__ void scan_tiles(uint64_t* status, int64_t ntiles, int
     __builtin_amdgcn_wave_barrier();
     if (advance == 0) {
       bool quit = false;
-      if (lane == 0) quit = wait_expired(t0, polls, ws);
+      if (lane == 0) quit = wait_expired(t0, polls, ws, ticks);
       if (__shfl((int)quit, 0, 64)) break;
       __builtin_amdgcn_s_sleep(2);
       continue;
@@ -496,8 +500,8 @@ __device__ __forceinline__ void flush_tile(const KArgs& a, int64_t tile, int cou
 // by decoupled look-back (LB == true; the owner of a call's last tile then writes its total).
 template <bool LB>
 __device__ __forceinline__ int64_t tile_prefix(const KArgs& a, int64_t tile, int agg) {
-  if (!LB) return wait_prefix(a.status, tile, a.ws);
-  const int64_t prefix = lookback_prefix(a.status, tile, agg, a.ws);
+  if (!LB) return wait_prefix(a.status, tile, a.ws, a.wait_ticks);
+  const int64_t prefix = lookback_prefix(a.status, tile, agg, a.ws, a.wait_ticks);
   if (tile == a.ntiles - 1 && __lane_id() == 0) *a.ototal = prefix + agg;
   return prefix;
 }
@@ -602,7 +606,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   const int64_t gw = (int64_t)blockIdx.x * NWAVE + wave;
   const int64_t W = (int64_t)gridDim.x * NWAVE - 1;
   if (gw == W) {
-    scan_tiles<scan_k<WPPT>()>(a.status, a.ntiles, a.ototal, a.ws,
+    scan_tiles<scan_k<WPPT>()>(a.status, a.ntiles, a.ototal, a.ws, a.wait_ticks,
                                reinterpret_cast<uint64_t*>(&sh.stage[wave]));
     return;
   }

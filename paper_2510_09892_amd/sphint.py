@@ -28,7 +28,7 @@ BATCH_RUN_MAX = 16  # SPHINT_BATCH_RUN_MAX
 AA_HIT, AA_DEGEN, AA_COPLANAR, AA_NONFINITE, AA_EXACT, AA_INTERNAL = 1, 4, 8, 16, 32, 64
 
 EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
-           "sphint_arc_constlat_noalloc",
+           "sphint_arc_constlat_noalloc", "sphint_set_wait_limit",
            "sphint_set_profile_events",
            "sphint_batch_plan_create", "sphint_batch_autotune", "sphint_batch_launch",
            "sphint_batch_params", "sphint_batch_set_params", "sphint_batch_check",
@@ -89,6 +89,8 @@ def load():
     lib.sphint_arc_constlat_noalloc.restype = ctypes.c_int
     lib.sphint_workspace_size.argtypes = [i64]
     lib.sphint_workspace_size.restype = sz
+    lib.sphint_set_wait_limit.argtypes = [ctypes.c_double]
+    lib.sphint_set_wait_limit.restype = ctypes.c_int
     lib.sphint_set_profile_events.argtypes = [vp, vp]
     lib.sphint_set_profile_events.restype = ctypes.c_int
     lib.sphint_check.argtypes = [vp, i64, i64]
@@ -331,6 +333,11 @@ def arc_constlat_noalloc(p1, p2, lat_z, lat_offsets=None, lat_idx=None, mode="ef
                                          _stream(stream))
     _check(st, "sphint_arc_constlat_noalloc")
     return out
+
+
+def set_wait_limit(seconds):
+    """sphint_set_wait_limit: the limit of every bounded wait inside later launches."""
+    _check(load().sphint_set_wait_limit(float(seconds)), "sphint_set_wait_limit")
 
 
 def candidates(p1, p2, lat_z, pad=0.0, stream=None):

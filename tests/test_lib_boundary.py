@@ -155,6 +155,13 @@ def test_batch_run_workspace_and_rejections():
     assert call([desc()], wsb=lib.sphint_batch_run_workspace_size(1, 4) - 1) == sphint.E_INVAL
 
 
+def test_wait_limit_validation():
+    lib = sphint.load()
+    for bad in (-1.0, float("nan"), float("inf"), 3601.0):
+        assert lib.sphint_set_wait_limit(bad) == sphint.E_INVAL
+    assert lib.sphint_set_wait_limit(2.0) == sphint.OK  # the default
+
+
 def test_batch_rejects_bad_arguments():
     lib = sphint.load()
     h = ctypes.c_void_p()
