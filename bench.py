@@ -351,17 +351,20 @@ def batch_measure(torch, sphint, devs, stats, modes, steps, warmup):
         byts = sum(48 * st[1] + 8 * (st[0] + 1) + 6 * st[2] + 8 * st[3] for st in stats) \
             + BYTES_PER_HIT * hits
         lb = plan.lookback()
+        share = plan.share()
         kname = (f"graph launch: k_batch<{1 if mode == 'eft' else 0},{plan.params()[0]},true,"
-                 f"{'true' if lb else 'false'}> with its init and pair-to-arc launches")
+                 f"{'true' if lb else 'false'},{'true' if share else 'false'}> with its init and "
+                 f"pair-to-arc launches")
         roof = roofline(mode, {"kernel_ms": dms, "total": hits, "hitpairs": hitpairs}, nnz, byts,
                         kname, None)
         res[mode] = dict(ms_per_step=t_batch * 1e3, device_ms=statistics.mean(dms),
                          per_mesh_ms=t_per * 1e3, speedup_vs_per_mesh=t_per / t_batch,
-                         params=plan.params(), lookback=lb, autotune_s=t_tune, hits=hits,
+                         params=plan.params(), lookback=lb, share_arcs=share,
+                         autotune_s=t_tune, hits=hits,
                          value=nnz / t_batch, roofline=roof)
         plan.close()
         log(f"[bench] batch {mode}: {t_batch * 1e3:.2f} ms (per-mesh launches {t_per * 1e3:.2f} ms), "
-            f"params {res[mode]['params']}")
+            f"params {res[mode]['params']}, look-back {lb}, shared arcs {share}")
     return res
 
 

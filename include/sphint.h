@@ -216,7 +216,8 @@ typedef struct sphint_plan sphint_plan;
 sphint_status sphint_batch_plan_create(const sphint_mesh_desc *meshes, int n_meshes,
                                        sphint_mode mode, sphint_plan **plan);
 /* Times the plan's candidate schedules (pairs per thread 1-4 x persistent grid sizes x the
- * two ways of ordering tile offsets, see sphint_batch_set_scan) by running the whole batch
+ * two ways of ordering tile offsets, see sphint_batch_set_scan; for an EFT plan over CSR
+ * lists also with arc records shared, see sphint_batch_set_share) by running the whole batch
  * on `stream`, keeps the fastest, and synchronizes the stream;
  * reads/appends a text cache at cache_path (may be NULL) keyed by the plan's shape.  The
  * batch's outputs are overwritten (with the same values). */
@@ -239,6 +240,15 @@ sphint_status sphint_batch_set_params(sphint_plan *plan, int pairs_per_thread, i
  * it re-captures the graph at the next launch. */
 sphint_status sphint_batch_scan(const sphint_plan *plan, int *lookback);
 sphint_status sphint_batch_set_scan(sphint_plan *plan, int lookback);
+/* Whether an EFT plan over CSR lists shares each arc's z0-free part among the arc's
+ * candidates (Alg. 8's normal, norms and F pairs, and the slope signs of the containment
+ * rule, Sec. 2, depend on the arc alone): 1 = a wavefront computes the records of 64
+ * consecutive arcs once, one arc per lane, and every pair of a tile row fetches its arc's
+ * record from the lane holding it; 0 = every pair computes its arc's part (the single-call
+ * path).  Results are identical, bit for bit.  SPHINT_E_INVAL for share = 1 on a naive or
+ * dense plan.  Setting it re-captures the graph at the next launch. */
+sphint_status sphint_batch_share(const sphint_plan *plan, int *share);
+sphint_status sphint_batch_set_share(sphint_plan *plan, int share);
 /* After the stream has completed a launch of the plan: SPHINT_E_DEVICE if a kernel of that
  * launch reported an internal limit (as sphint_check), else SPHINT_E_CAPACITY if some mesh's
  * *out_total exceeds its out.capacity, else SPHINT_OK.  Synchronous (reads the plan's error

@@ -31,7 +31,7 @@
 
 using namespace sphint;
 
-template <int MODE, int PPT, bool CSR, bool LB>
+template <int MODE, int PPT, bool CSR, bool LB, bool SHARE = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(const KArgs* __restrict__ args,
                                                  const int64_t* __restrict__ tile_base,
                                                  int n_meshes, int64_t total_tiles) {
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   }
   int64_t t = gw;
   int mesh = 0;  // tiles only increase, so the mesh index only moves forward
-  wave_loop<MODE, PPT, CSR, flush_at<MODE, PPT>(), LB>(args, sh, [&](int& m, int64_t& tile) {
+  wave_loop<MODE, PPT, CSR, flush_at<MODE, PPT>(), LB, SHARE>(args, sh, [&](int& m, int64_t& tile) {
     if (t >= total_tiles) return false;
     while (mesh + 1 < n_meshes && tile_base[mesh + 1] <= t) ++mesh;
     m = mesh;
@@ -81,6 +81,7 @@ struct sphint_plan {
   int ppt = 1;
   int wg_per_cu = 0;  // resident workgroups per CU (0: as many as fit)
   bool lookback = false;  // tile offsets by decoupled look-back instead of the scanner
+  bool share = false;     // EFT over CSR lists: arc records shared by a tile's rows
   // device state
   KArgs* d_args = nullptr;
   int64_t* d_tile_base = nullptr;
@@ -96,12 +97,13 @@ struct sphint_plan {
 
 namespace {
 
-template <int MODE, int PPT, bool CSR, bool LB = false>
+template <int MODE, int PPT, bool CSR, bool LB = false, bool SHARE = false>
 int max_resident() {
   static std::atomic<int> cached{0};  // queried once; calls may come from several threads
   int blocks = cached.load(std::memory_order_relaxed);
   if (blocks) return blocks;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MODE, PPT, CSR, LB>, BLOCK, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<MODE, PPT, CSR, LB, SHARE>,
+                                                   BLOCK, 0) !=
           hipSuccess ||
       blocks <= 0)
     blocks = 1;
@@ -122,6 +124,9 @@ int resident_per_cu_form(sphint_mode mode, int ppt) {
   if (ppt == 3) return max_resident<0, 3, CSR, LB>();
   return max_resident<0, 4, CSR, LB>();
 }
+
+// Arc records are shared in EFT mode over CSR lists only.
+bool can_share(const sphint_plan* p) { return p->mode == SPHINT_EFT_FP64 && p->csr; }
 
 void drop_graph(sphint_plan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -168,7 +173,16 @@ sphint_status layout(sphint_plan* p) {
   return SPHINT_OK;
 }
 
-int resident_per_cu(const sphint_plan* p, int ppt, bool lb) {
+template <bool LB>
+int resident_per_cu_share(int ppt) {
+  if (ppt == 1) return max_resident<1, 1, true, LB, true>();
+  if (ppt == 2) return max_resident<1, 2, true, LB, true>();
+  if (ppt == 3) return max_resident<1, 3, true, LB, true>();
+  return max_resident<1, 4, true, LB, true>();
+}
+
+int resident_per_cu(const sphint_plan* p, int ppt, bool lb, bool share) {
+  if (share) return lb ? resident_per_cu_share<true>(ppt) : resident_per_cu_share<false>(ppt);
   if (lb)
     return p->csr ? resident_per_cu_form<true, true>(p->mode, ppt)
                   : resident_per_cu_form<false, true>(p->mode, ppt);
@@ -178,7 +192,10 @@ int resident_per_cu(const sphint_plan* p, int ppt, bool lb) {
 
 template <int MODE, int PPT, bool LB>
 void launch_batch_lb(const sphint_plan* p, unsigned grid, hipStream_t st) {
-  if (p->csr)
+  if (MODE == 1 && p->csr && p->share)
+    hipLaunchKernelGGL((k_batch<1, PPT, true, LB, true>), dim3(grid), dim3(BLOCK), 0, st,
+                       p->d_args, p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
+  else if (p->csr)
     hipLaunchKernelGGL((k_batch<MODE, PPT, true, LB>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
                        p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
   else
@@ -213,7 +230,7 @@ sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
     }
   if (p->total_tiles > 0) {
     // every wavefront of the grid must be resident at once (see k_batch)
-    const int res = resident_per_cu(p, p->ppt, p->lookback);
+    const int res = resident_per_cu(p, p->ppt, p->lookback, p->share);
     const int per_cu = p->wg_per_cu > 0 && p->wg_per_cu < res ? p->wg_per_cu : res;
     int64_t grid = (p->total_tiles + (p->lookback ? 0 : 1) + NWAVE - 1) / NWAVE;  // + scanner
     if ((int64_t)per_cu * p->cus < grid) grid = (int64_t)per_cu * p->cus;
@@ -321,13 +338,14 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
         if (!bar) continue;
         *bar = 0;
         if (key == line) {
-          int ppt = 0, wg = -1, lb = 0;
-          if (sscanf(bar + 1, "%d %d %d", &ppt, &wg, &lb) >= 2 && (ppt >= 1 && ppt <= 4) &&
-              wg >= 0 && (lb == 0 || lb == 1)) {
+          int ppt = 0, wg = -1, lb = 0, sh = 0;
+          if (sscanf(bar + 1, "%d %d %d %d", &ppt, &wg, &lb, &sh) >= 2 && (ppt >= 1 && ppt <= 4) &&
+              wg >= 0 && (lb == 0 || lb == 1) && (sh == 0 || (sh == 1 && can_share(p)))) {
             fclose(f);
             p->ppt = ppt;
             p->wg_per_cu = wg;
             p->lookback = lb == 1;
+            p->share = sh == 1;
             return layout(p);
           }
         }
@@ -347,18 +365,22 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
   hipEvent_t e0 = ev.e0, e1 = ev.e1;
   float best = 1e30f;
   int best_ppt = 1, best_wg = 0;
-  bool best_lb = false;
+  bool best_lb = false, best_share = false;
   const int ppts[4] = {1, 2, 3, 4};
-  for (int ci = 0; ci < 8; ++ci) {
-    const bool lb = ci >= 4;
+  const int ncand = can_share(p) ? 16 : 8;
+  for (int ci = 0; ci < ncand; ++ci) {
+    const bool lb = (ci & 4) != 0;
+    const bool share = ci >= 8;
     const int ppt = ppts[ci & 3];
-    const int res = resident_per_cu(p, ppt, lb);
+    if (share && ppt == 1) continue;  // one-row tiles share nothing across rows
+    const int res = resident_per_cu(p, ppt, lb, share);
     const int wgs[4] = {res, res > 1 ? res - 1 : 1, res > 2 ? res / 2 : 1, 1};
     for (int wi = 0; wi < 4; ++wi) {
       if (wi > 0 && wgs[wi] == wgs[wi - 1]) continue;
       p->ppt = ppt;
       p->wg_per_cu = wgs[wi];
       p->lookback = lb;
+      p->share = share;
       sphint_status s = layout(p);
       if (s != SPHINT_OK) return s;
       if (enqueue(p, st) != SPHINT_OK) return SPHINT_E_HIP;  // warm-up
@@ -374,17 +396,20 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
         best_ppt = ppt;
         best_wg = wgs[wi];
         best_lb = lb;
+        best_share = share;
       }
     }
   }
   p->ppt = best_ppt;
   p->wg_per_cu = best_wg;
   p->lookback = best_lb;
+  p->share = best_share;
   sphint_status s = layout(p);
   if (s == SPHINT_OK && cache_path) {
     FILE* f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "%s|%d %d %d\n", key.c_str(), best_ppt, best_wg, best_lb ? 1 : 0);
+      fprintf(f, "%s|%d %d %d %d\n", key.c_str(), best_ppt, best_wg, best_lb ? 1 : 0,
+              best_share ? 1 : 0);
       fclose(f);
     }
   }
@@ -418,6 +443,18 @@ extern "C" sphint_status sphint_batch_scan(const sphint_plan* p, int* lookback) 
 extern "C" sphint_status sphint_batch_set_scan(sphint_plan* p, int lookback) {
   if (!p || (lookback != 0 && lookback != 1)) return SPHINT_E_INVAL;
   p->lookback = lookback == 1;
+  return layout(p);
+}
+
+extern "C" sphint_status sphint_batch_share(const sphint_plan* p, int* share) {
+  if (!p || !share) return SPHINT_E_INVAL;
+  *share = p->share ? 1 : 0;
+  return SPHINT_OK;
+}
+
+extern "C" sphint_status sphint_batch_set_share(sphint_plan* p, int share) {
+  if (!p || (share != 0 && share != 1) || (share == 1 && !can_share(p))) return SPHINT_E_INVAL;
+  p->share = share == 1;
   return layout(p);
 }
 

@@ -37,6 +37,76 @@ extern "C" int sphint_hostcheck_eval(int mode, int64_t n, const double* x1, cons
   return 0;
 }
 
+// CSR lists in EFT mode with the arc part shared, as the batched kernels' shared path
+// evaluates them: each arc's record once (exact slope signs where the filters are open),
+// then every candidate from its arc's record; the points run for every pair and are kept
+// where there are hits.  lat_idx entries outside [0, n_lat) give z0 = NaN.  *open_arcs
+// receives the number of arcs whose slope filters left a sign open.
+extern "C" int sphint_hostcheck_eval_shared(int64_t n_arcs, const double* x1, const double* y1,
+                                            const double* z1, const double* x2,
+                                            const double* y2, const double* z2,
+                                            const double* lat_z, int64_t n_lat,
+                                            const int64_t* off, const int32_t* idx,
+                                            int32_t* count, int32_t* flags, int32_t* r0,
+                                            int32_t* r1, double* px0, double* py0, double* px1,
+                                            double* py1, int64_t* open_arcs) {
+  using namespace sphint;
+  static thread_local double arena[xp::ARENA];
+  int64_t opened = 0;
+  for (int64_t a = 0; a < n_arcs; ++a) {
+    ArcDec D;
+    ArcPts P;
+    int d1, d2;
+    arc_shared(x1[a], y1[a], z1[a], x2[a], y2[a], z2[a], D, P, d1, d2);
+    if (d1 == UNDECIDED || d2 == UNDECIDED) {
+      ++opened;
+      D.meta = arc_resolve(D.meta, d1, d2, x1[a], y1[a], z1[a], x2[a], y2[a], z2[a], arena);
+    } else {
+      D.meta = arc_meta(D.meta, d1, d2, false, false, false);
+    }
+    auto xy = [&](int e) { return e == 1 ? dd{x1[a], y1[a]} : dd{x2[a], y2[a]}; };
+    for (int64_t k = off[a]; k < off[a + 1]; ++k) {
+      const int32_t li = idx[k];
+      const double z0 = li >= 0 && li < n_lat ? lat_z[li] : __builtin_nan("");
+      Decisions dec = {0, 0, 0, 0, 0};
+      S2Eft S;
+      PairOut o = decide_shared<false>(true, D, z0, dec, S, xy);
+      if (o.flags & F_NEEDEXACT) {
+        const bool ok = resolve_exact_shared(dec, D.meta, x1[a], y1[a], z1[a], x2[a], y2[a],
+                                             z2[a], z0, arena);
+        o = decide_shared<true>(true, D, z0, dec, S, xy);
+        if (!ok) o.flags |= F_INTERNAL;
+      }
+      PairOut q = o;
+      points_eft_g(
+          [&](int t) {
+            switch (t) {
+              case 0: return P.Fx;
+              case 1: return P.eFx;
+              case 2: return P.Fy;
+              case 3: return P.eFy;
+              case 4: return P.nx;
+              case 5: return P.enx;
+              case 6: return P.ny;
+              default: return P.eny;
+            }
+          },
+          D.S2, z0, S, q);
+      if (o.count) o = q;
+      count[k] = o.count;
+      flags[k] = (int32_t)o.flags;
+      r0[k] = o.r0;
+      r1[k] = o.r1;
+      px0[k] = o.px0;
+      py0[k] = o.py0;
+      px1[k] = o.px1;
+      py1[k] = o.py1;
+    }
+  }
+  if (open_arcs) *open_arcs = opened;
+  return 0;
+}
+
 // Exact sign of one predicate (sphint::PRED_*), for tests of the expansion arithmetic.
 extern "C" int sphint_hostcheck_exact_sign(int which, double x1, double y1, double z1, double x2,
                                            double y2, double z2, double z0) {

@@ -312,6 +312,8 @@ struct TileRegs {
 // tile (the pair is tile base + o).
 struct RowIn {
   double x1, y1, z1, x2, y2, z2, z0;
+  int64_t arc;  // CSR: the pair's arc (clamped); rows evaluated from shared arc records
+                // load only this, not the endpoints
   uint32_t o;
   bool valid;
 };
@@ -334,7 +336,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const KArgs& a, int64_t tile) {
 // stays in flight while the current row is evaluated.  CSR calls take each pair's arc from
 // the pair-to-arc table that k_pair_arcs wrote (clamped, so malformed offsets cannot send
 // a read out of bounds).
-template <bool CSR>
+template <bool CSR, bool SHARE = false>
 __device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int j) {
   RowIn r;
   // offsets stay below 1024 (a tile has at most 1024 pairs); the mask tells the compiler
@@ -349,8 +351,11 @@ __device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int 
     const bool ok = li >= 0 && li < a.n_lat;
     const double z = gptr(a.lat_z)[ok ? li : 0];
     r.z0 = ok ? z : __builtin_nan("");
-    r.x1 = gptr(a.x1)[arc]; r.y1 = gptr(a.y1)[arc]; r.z1 = gptr(a.z1)[arc];
-    r.x2 = gptr(a.x2)[arc]; r.y2 = gptr(a.y2)[arc]; r.z2 = gptr(a.z2)[arc];
+    r.arc = arc;
+    if (!SHARE) {
+      r.x1 = gptr(a.x1)[arc]; r.y1 = gptr(a.y1)[arc]; r.z1 = gptr(a.z1)[arc];
+      r.x2 = gptr(a.x2)[arc]; r.y2 = gptr(a.y2)[arc]; r.z2 = gptr(a.z2)[arc];
+    }
   } else {
     r.z0 = gptr(a.lat_z + c.base)[oc];
     r.x1 = gptr(a.x1 + c.base)[oc]; r.y1 = gptr(a.y1 + c.base)[oc];
@@ -450,6 +455,165 @@ __device__ __forceinline__ void eval_row(const KArgs& a, const TileCtx& c, const
   r.agg += __popcll(b1) + __popcll(b2);
 }
 
+// ------------------------------------------------------ arc records shared in registers
+//
+// CSR lists hold an arc's candidates next to each other, so a few rows of a tile share a
+// few dozen arcs.  With the arc part shared (EFT mode), a wavefront keeps a window of 64
+// consecutive arcs of one mesh, lane l holding the record (ArcDec, ArcPts) of arc
+// base + l, computed once by the whole wavefront; each lane of a row fetches its arc's
+// record from the lane that holds it (ds_bpermute) instead of recomputing it from the
+// endpoints.  A row whose arcs are not all in the window gets a new window starting at its
+// first arc.  A row spanning more than 64 arc ids (arcs without candidates between its
+// pairs) cannot share: every lane then computes its own arc's record into the window
+// registers (the per-pair cost), and the next row starts a new window.
+
+struct ArcWin {
+  ArcDec d;
+  ArcPts p;
+  int64_t base;  // wavefront-uniform
+  int mesh;      // mesh of the window (-1: none)
+};
+
+__device__ __forceinline__ double bperm_d(int addr, double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// addr = 4 * source lane; every lane of the wavefront must be active.
+__device__ __forceinline__ ArcDec fetch_dec(const ArcDec& s, int addr) {
+  ArcDec d;
+  d.S2 = bperm_d(addr, s.S2); d.s2 = bperm_d(addr, s.s2);
+  d.S3 = bperm_d(addr, s.S3); d.s3 = bperm_d(addr, s.s3);
+  d.side = bperm_d(addr, s.side);
+  d.z1 = bperm_d(addr, s.z1); d.z2 = bperm_d(addr, s.z2);
+  d.n21 = bperm_d(addr, s.n21); d.n22 = bperm_d(addr, s.n22);
+  d.meta = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)s.meta);
+  return d;
+}
+
+__device__ __forceinline__ ArcPts fetch_pts(const ArcPts& s, int addr) {
+  ArcPts p;
+  p.Fx = bperm_d(addr, s.Fx); p.eFx = bperm_d(addr, s.eFx);
+  p.Fy = bperm_d(addr, s.Fy); p.eFy = bperm_d(addr, s.eFy);
+  p.nx = bperm_d(addr, s.nx); p.enx = bperm_d(addr, s.enx);
+  p.ny = bperm_d(addr, s.ny); p.eny = bperm_d(addr, s.eny);
+  return p;
+}
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Each lane computes the record of arc `arc` (< a.n_arcs) into the window registers; open
+// slope filters get exact signs one lane at a time.
+template <class Shared>
+__device__ __forceinline__ void fill_window(const KArgs& a, int64_t arc, ArcWin& w, Shared& sh) {
+  const double x1 = gptr(a.x1)[arc], y1 = gptr(a.y1)[arc], z1 = gptr(a.z1)[arc];
+  const double x2 = gptr(a.x2)[arc], y2 = gptr(a.y2)[arc], z2 = gptr(a.z2)[arc];
+  int d1, d2;
+  arc_shared(x1, y1, z1, x2, y2, z2, w.d, w.p, d1, d2);
+  const bool open = d1 == UNDECIDED || d2 == UNDECIDED;
+  unsigned meta = arc_meta(w.d.meta, d1, d2, false, false, false);
+  resolve_serial(open, [&] {
+    lds_lock(&sh.lock);
+    meta = arc_resolve(w.d.meta, d1, d2, x1, y1, z1, x2, y2, z2, sh.arena);
+    lds_unlock(&sh.lock);
+  });
+  w.d.meta = meta;
+}
+
+// eval_row for rows evaluated from arc records (EFT mode, CSR lists) of mesh m.
+template <int WPPT, class Shared>
+__device__ __forceinline__ void eval_row_shared(const KArgs& a, int m, const TileCtx& c,
+                                                const RowIn& in, int j, TileRegs<WPPT>& r,
+                                                Shared& sh, ArcWin& w) {
+  const int lane = __lane_id();
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const unsigned long long vm = __ballot(in.valid);
+  int64_t d = in.arc - w.base;
+  if (__ballot(in.valid && w.mesh == m && d >= 0 && d < 64) != vm) {  // wavefront-uniform
+    // the row's first arc (a row holds at least one valid pair)
+    const int64_t b = readlane64(in.arc, __ffsll(vm) - 1);
+    d = in.arc - b;
+    if (__ballot(in.valid && d >= 0 && d < 64) == vm) {  // a new window holds the row
+      const int64_t arc = b + lane;
+      fill_window(a, arc < a.n_arcs ? arc : a.n_arcs - 1, w, sh);
+      w.base = b;
+      w.mesh = m;
+    } else {  // every lane its own arc
+      fill_window(a, in.arc, w, sh);
+      d = lane;
+      w.mesh = -1;
+    }
+  }
+  int src = ((int)d & 63) << 2;
+  auto xy = [&](int e) {
+    return e == 1 ? dd{gptr(a.x1)[in.arc], gptr(a.y1)[in.arc]}
+                  : dd{gptr(a.x2)[in.arc], gptr(a.y2)[in.arc]};
+  };
+  Decisions dec = {0, 0, 0, 0, 0};
+  S2Eft S;
+  PairOut& o = r.o[j];
+  ArcDec D = fetch_dec(w.d, src);
+  o = decide_shared<false>(in.valid, D, in.z0, dec, S, xy);
+  const bool need = (o.flags & F_NEEDEXACT) != 0;
+  if (__ballot(need)) {  // rare
+    // Exact signs for the open decisions.  The window is made again afterwards (every lane
+    // its own arc), so none of its registers has to survive the expansion arithmetic.
+    bool ok = true;
+    const unsigned meta = D.meta;
+    resolve_serial(need, [&] {
+      const int64_t k = in.arc;
+      lds_lock(&sh.lock);
+      ok = resolve_exact_shared(dec, meta, gptr(a.x1)[k], gptr(a.y1)[k], gptr(a.z1)[k],
+                                gptr(a.x2)[k], gptr(a.y2)[k], gptr(a.z2)[k], in.z0, sh.arena);
+      lds_unlock(&sh.lock);
+    });
+    fill_window(a, in.arc, w, sh);
+    w.mesh = -1;
+    src = lane << 2;
+    D = fetch_dec(w.d, src);
+    if (need) {
+      o = decide_shared<true>(in.valid, D, in.z0, dec, S, xy);
+      if (!ok) o.flags |= F_INTERNAL;
+    }
+  }
+  // every lane runs the points (their terms come from other lanes, which must all be
+  // active); only lanes with hits keep them
+  PairOut q = o;
+  points_eft_g(
+      [&](int k) {
+        switch (k) {
+          case 0: return bperm_d(src, w.p.Fx);
+          case 1: return bperm_d(src, w.p.eFx);
+          case 2: return bperm_d(src, w.p.Fy);
+          case 3: return bperm_d(src, w.p.eFy);
+          case 4: return bperm_d(src, w.p.nx);
+          case 5: return bperm_d(src, w.p.enx);
+          case 6: return bperm_d(src, w.p.ny);
+          default: return bperm_d(src, w.p.eny);
+        }
+      },
+      D.S2, in.z0, S, q);
+  if (o.count) o = q;
+  if (o.flags & F_INTERNAL) atomicOr(a.ws + 1, ERR_EXACT);
+  const int cnt = in.valid ? o.count : 0;
+  o.count = cnt;
+  if (in.valid) {
+    gptr(a.ocount + c.base)[in.o] = (uint8_t)cnt;
+    if (a.oflags) gptr(a.oflags + c.base)[in.o] = (uint8_t)o.flags;
+  }
+  const unsigned long long b1 = __ballot(cnt >= 1);
+  const unsigned long long b2 = __ballot(cnt >= 2);
+  if (j == 0) r.agg = 0;
+  r.woff[j] = r.agg + __popcll(b1 & lt) + __popcll(b2 & lt);
+  r.agg += __popcll(b1) + __popcll(b2);
+}
+
 // Moves row j's hits from registers into the wavefront's staging buffer.
 template <int WPPT>
 __device__ __forceinline__ void stage_row(const TileRegs<WPPT>& r, int j, WaveStage<WPPT>& st) {
@@ -513,9 +677,10 @@ __device__ __forceinline__ int64_t tile_prefix(const KArgs& a, int64_t tile, int
 // first FLUSH_AT rows of the next tile, which gives the scanner that much time to publish
 // its offset.  Rows evaluated after that point go straight to the staging buffer, so at most
 // FLUSH_AT rows of results are held in registers.
-template <int MODE, int WPPT, bool CSR, int FLUSH_AT, bool LB, class Next>
+template <int MODE, int WPPT, bool CSR, int FLUSH_AT, bool LB, bool SHARE = false, class Next>
 __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT, CSR>& sh,
                                           Next&& next) {
+  static_assert(!SHARE || (MODE == 1 && CSR), "arc records are shared in EFT mode over CSR lists");
   static_assert(FLUSH_AT >= 1 && FLUSH_AT <= WPPT, "flush point inside the tile");
   static_assert(WPPT <= 16, "pair and hit offsets within a tile are masked to 10 and 11 bits");
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront-uniform
@@ -530,14 +695,17 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
   if (!have) return;
   m = __builtin_amdgcn_readfirstlane(m);  // wavefront-uniform: the arguments load as scalars
   TileCtx ctx = tile_ctx<WPPT, CSR>(args[m], tile), ctx2;
-  RowIn cur = load_row<CSR>(args[m], ctx, 0), nxt;
+  RowIn cur = load_row<CSR, SHARE>(args[m], ctx, 0), nxt;
+  ArcWin win;
+  win.base = 0;
+  win.mesh = -1;
   while (have) {
     const KArgs& a = args[m];
     bool have2 = false;
 #pragma unroll
     for (int j = 0; j < WPPT; ++j) {
       if (j + 1 < WPPT) {
-        nxt = load_row<CSR>(a, ctx, j + 1);
+        nxt = load_row<CSR, SHARE>(a, ctx, j + 1);
       } else {
         // always fetch ahead; past the last tile the fetch repeats this tile (unused)
         have2 = next(m2, tile2);
@@ -547,9 +715,12 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
         }
         m2 = __builtin_amdgcn_readfirstlane(m2);
         ctx2 = tile_ctx<WPPT, CSR>(args[m2], tile2);
-        nxt = load_row<CSR>(args[m2], ctx2, 0);
+        nxt = load_row<CSR, SHARE>(args[m2], ctx2, 0);
       }
-      eval_row<MODE, WPPT>(a, ctx, cur, j, r, sh);
+      if constexpr (SHARE)
+        eval_row_shared<WPPT>(a, m, ctx, cur, j, r, sh, win);
+      else
+        eval_row<MODE, WPPT>(a, ctx, cur, j, r, sh);
       if (j + 1 == FLUSH_AT) {
         if (pending) {
           const KArgs& pa = args[pm];

@@ -270,13 +270,17 @@ __host__ __device__ __forceinline__ S2Eft s2_eft(const ArcEft& a, double z0) {
 //          arcs near a pole, where heights differ from z0 by a few ulps of 1, stage 1 leaves
 //          a few percent of pairs open, and this stage settles them for a third of the cost
 //          of a full compensated dot product.
-__host__ __device__ __forceinline__ int height_cmp(double z0, double z, double n2, double zz,
-                                                   double x, double y, dd C) {
+// The endpoint's x and y are needed by stage 2 only; xy() supplies them (as {x, y}).
+template <class XY>
+__host__ __device__ __forceinline__ int height_cmp_xy(double z0, double z, double n2, double zz,
+                                                      dd C, XY&& xy) {
   if (z0 == 0.0) return -sgn(z);
   if (z == 0.0 || ((z0 > 0.0) != (z > 0.0))) return sgn(z0);
   const double mag = C.hi * n2 + zz;
   const double t = __builtin_fma(C.hi, n2, -zz);
   if (__builtin_fabs(t) > 0x1p-49 * mag) return sgn(z0) * sgn(t);
+  const dd e = xy();
+  const double x = e.hi, y = e.lo;
   const dd X = two_prod(x, x), Y = two_prod(y, y), Z = two_prod(z, z);
   const dd s1 = two_sum(X.hi, Y.hi);
   const dd s2 = two_sum(s1.hi, Z.hi);
@@ -287,6 +291,11 @@ __host__ __device__ __forceinline__ int height_cmp(double z0, double z, double n
   const double w = h.hi + (((h.lo + P.lo) - Z.lo) + rest);
   if (__builtin_fabs(w) > 0x1p-92 * mag) return sgn(z0) * sgn(w);
   return UNDECIDED;
+}
+
+__host__ __device__ __forceinline__ int height_cmp(double z0, double z, double n2, double zz,
+                                                   double x, double y, dd C) {
+  return height_cmp_xy(z0, z, n2, zz, C, [&] { return dd{x, y}; });
 }
 
 // Alg. 2 (CompDot) over six TwoProducts in Alg. 8's term order, split in two: the running
@@ -318,24 +327,47 @@ __host__ __device__ __forceinline__ double comp_dot_tail(CdState c, dd t2, dd t3
 // lower-sign root is AccuX with (s, e_s) negated, so its TwoProducts are the exact negations
 // of the upper root's: the products are formed once, with the sign of the first root, and a
 // second root (always the other sign) reuses them negated.  The z0 terms open both CompDots.
-__host__ __device__ __forceinline__ void points_eft(const ArcEft& a, double z0, const S2Eft& s2,
-                                                    PairOut& o) {
+// g(k) supplies the arc's terms when they are first needed: k = 0..7 for Fx, e_Fx, Fy, e_Fy,
+// n_x, e_nx, n_y, e_ny.
+template <class G>
+__host__ __device__ __forceinline__ void points_eft_g(G&& g, double S2, double z0,
+                                                      const S2Eft& s2, PairOut& o) {
   const dd sq = acc_sqrt(s2.ss, s2.ess);
-  const CdState hx = comp_dot_head(two_prod(a.Fx, z0), two_prod(a.eFx, z0));
-  const CdState hy = comp_dot_head(two_prod(a.Fy, z0), two_prod(a.eFy, z0));
+  const CdState hx = comp_dot_head(two_prod(g(0), z0), two_prod(g(1), z0));
+  const CdState hy = comp_dot_head(two_prod(g(2), z0), two_prod(g(3), z0));
   const bool plus0 = o.r0 == ROOT_PLUS;
   const double sb = plus0 ? sq.hi : -sq.hi;
   const double es = plus0 ? sq.lo : -sq.lo;
-  const dd x2 = two_prod(a.ny, sb), x3 = two_prod(a.eny, sb);
-  const dd x4 = two_prod(a.ny, es), x5 = two_prod(a.eny, es);
-  const dd y2 = two_prod(-a.nx, sb), y3 = two_prod(-a.enx, sb);
-  const dd y4 = two_prod(-a.nx, es), y5 = two_prod(-a.enx, es);
-  o.px0 = -(comp_dot_tail(hx, x2, x3, x4, x5, 1.0) / a.S2);
-  o.py0 = -(comp_dot_tail(hy, y2, y3, y4, y5, 1.0) / a.S2);
+  const double ny = g(6), eny = g(7);
+  const dd x2 = two_prod(ny, sb), x3 = two_prod(eny, sb);
+  const dd x4 = two_prod(ny, es), x5 = two_prod(eny, es);
+  const double nx = g(4), enx = g(5);
+  const dd y2 = two_prod(-nx, sb), y3 = two_prod(-enx, sb);
+  const dd y4 = two_prod(-nx, es), y5 = two_prod(-enx, es);
+  o.px0 = -(comp_dot_tail(hx, x2, x3, x4, x5, 1.0) / S2);
+  o.py0 = -(comp_dot_tail(hy, y2, y3, y4, y5, 1.0) / S2);
   if (o.count == 2) {
-    o.px1 = -(comp_dot_tail(hx, x2, x3, x4, x5, -1.0) / a.S2);
-    o.py1 = -(comp_dot_tail(hy, y2, y3, y4, y5, -1.0) / a.S2);
+    o.px1 = -(comp_dot_tail(hx, x2, x3, x4, x5, -1.0) / S2);
+    o.py1 = -(comp_dot_tail(hy, y2, y3, y4, y5, -1.0) / S2);
   }
+}
+
+__host__ __device__ __forceinline__ void points_eft(const ArcEft& a, double z0, const S2Eft& s2,
+                                                    PairOut& o) {
+  points_eft_g(
+      [&](int k) {
+        switch (k) {
+          case 0: return a.Fx;
+          case 1: return a.eFx;
+          case 2: return a.Fy;
+          case 3: return a.eFy;
+          case 4: return a.nx;
+          case 5: return a.enx;
+          case 6: return a.ny;
+          default: return a.eny;
+        }
+      },
+      a.S2, z0, s2, o);
 }
 
 // ====================================================================== pair drivers
@@ -438,6 +470,164 @@ __host__ __device__ __forceinline__ PairOut eval_eft(bool valid, double x1, doub
   }
   return o;
 }
+
+// ====================================================== EFT mode, arc part shared
+//
+// In a CSR list an arc has several candidate latitudes, and everything of Alg. 8 before z0
+// enters (the normal, its norms and the F pairs), as well as the slope signs d1, d2 of the
+// containment rule, depends on the arc alone.  ArcDec and ArcPts hold what the z0-dependent
+// steps read of an arc (the decisions, then the points); an arc's record is computed once
+// (arc_shared, then exact signs for open slope filters) and every candidate of the arc is
+// evaluated from it.  The result equals eval_eft on the pair's endpoints bit for bit and
+// flag for flag: the same functions run on the same values, and a pair that the per-pair
+// evaluation would send to the exact fallback (an open filter on a pair not certainly
+// without intersection) takes the forced path here too.
+
+struct ArcDec {
+  double S2, s2, S3, s3, side;  // s^2 block (Alg. 8 lines 7-11) and its filter
+  double z1, z2, n21, n22;      // height comparisons
+  unsigned meta;                // arc flags (bits 0-7) and the ARC_* bits
+};
+
+struct ArcPts {
+  double Fx, eFx, Fy, eFy;  // Alg. 8 lines 13-16 / 18-21
+  double nx, enx, ny, eny;  // the root numerators' s terms
+};
+
+enum : unsigned {
+  ARC_D1_SHIFT = 8,      // d1 + 1 in bits 8-9
+  ARC_D2_SHIFT = 10,     // d2 + 1 in bits 10-11
+  ARC_OPEN1 = 1u << 12,  // the d1 filter was open (d1 is the exact sign)
+  ARC_OPEN2 = 1u << 13,
+  ARC_XOVER = 1u << 14,  // an exact slope sign exceeded the arena (taken as 0)
+};
+
+// The shared part of one arc; d1, d2 come back from the filters (UNDECIDED where open).
+__host__ __device__ __forceinline__ void arc_shared(double x1, double y1, double z1, double x2,
+                                                    double y2, double z2, ArcDec& D, ArcPts& P,
+                                                    int& d1, int& d2) {
+  ArcEft A;
+  arc_eft(x1, y1, z1, x2, y2, z2, A);
+  d1 = d2 = 0;
+  D.meta = A.flags;
+  D.S2 = D.s2 = D.S3 = D.s3 = D.side = D.z1 = D.z2 = D.n21 = D.n22 = 0.0;
+  P.Fx = P.eFx = P.Fy = P.eFy = P.nx = P.enx = P.ny = P.eny = 0.0;
+  if (A.flags) return;
+  D.S2 = A.S2; D.s2 = A.s2; D.S3 = A.S3; D.s3 = A.s3; D.side = A.side;
+  D.z1 = A.z1; D.z2 = A.z2; D.n21 = A.n21; D.n22 = A.n22;
+  P.Fx = A.Fx; P.eFx = A.eFx; P.Fy = A.Fy; P.eFy = A.eFy;
+  P.nx = A.nx; P.enx = A.enx; P.ny = A.ny; P.eny = A.eny;
+  d1 = d_sign(A, x1, y1);
+  d2 = d_sign(A, x2, y2);
+}
+
+// The meta word once both slope signs are final.
+__host__ __device__ __forceinline__ unsigned arc_meta(unsigned flags, int d1, int d2, bool open1,
+                                                      bool open2, bool xover) {
+  return (flags & 0xffu) | ((unsigned)(d1 + 1) << ARC_D1_SHIFT) |
+         ((unsigned)(d2 + 1) << ARC_D2_SHIFT) | (open1 ? ARC_OPEN1 : 0u) |
+         (open2 ? ARC_OPEN2 : 0u) | (xover ? ARC_XOVER : 0u);
+}
+
+__host__ __device__ __forceinline__ int arc_d(unsigned meta, int shift) {
+  return (int)((meta >> shift) & 3u) - 1;
+}
+
+// Exact slope signs of an arc whose filters left them open (all six endpoint coordinates
+// are finite and the arc is not degenerate, or arc_shared would have flagged it).
+__host__ __device__ __forceinline__ unsigned arc_resolve(unsigned flags, int d1, int d2,
+                                                         double x1, double y1, double z1,
+                                                         double x2, double y2, double z2,
+                                                         double* arena) {
+  const bool o1 = d1 == UNDECIDED, o2 = d2 == UNDECIDED;
+  bool xo = false;
+  if (o1) {
+    d1 = exact_sign(PRED_D1, x1, y1, z1, x2, y2, z2, 0.0, arena);
+    if (d1 == 2) { xo = true; d1 = 0; }
+  }
+  if (o2) {
+    d2 = exact_sign(PRED_D2, x1, y1, z1, x2, y2, z2, 0.0, arena);
+    if (d2 == 2) { xo = true; d2 = 0; }
+  }
+  return arc_meta(flags, d1, d2, o1, o2, xo);
+}
+
+// Decisions and hit count of one pair from its arc's record (eval_eft_core without the
+// points).  FORCED == false: filters (F_NEEDEXACT when one is open); FORCED == true: the
+// decisions in `dec`.  S receives the s^2 pair the points use; xy(i) gives endpoint i's
+// (x, y) for the second stage of a height comparison.
+template <bool FORCED, class XY>
+__host__ __device__ __forceinline__ PairOut decide_shared(bool valid, const ArcDec& D, double z0,
+                                                          Decisions& dec, S2Eft& S, XY&& xy) {
+  PairOut o;
+  o.count = 0;
+  o.r0 = o.r1 = 0;
+  o.px0 = o.py0 = o.px1 = o.py1 = 0.0;
+  o.flags = 0;
+  S.ss = S.ess = 0.0;
+  S.sign = 0;
+  if (!valid) return o;
+  const unsigned af = D.meta & 0xffu;
+  if (af) {
+    o.flags = af;
+    return o;
+  }
+  if (!finite(z0)) {
+    o.flags = F_NONFINITE;
+    return o;
+  }
+  ArcEft A;
+  A.S2 = D.S2; A.s2 = D.s2; A.S3 = D.S3; A.s3 = D.s3; A.side = D.side;
+  S = s2_eft(A, z0);
+  if (!FORCED) dec.s2 = S.sign;
+  if (dec.s2 < 0) return o;
+  if (!FORCED) {
+    dec.d1 = (D.meta & ARC_OPEN1) ? UNDECIDED : arc_d(D.meta, ARC_D1_SHIFT);
+    dec.d2 = (D.meta & ARC_OPEN2) ? UNDECIDED : arc_d(D.meta, ARC_D2_SHIFT);
+    const dd C = two_prod(z0, z0);
+    dec.c1 = height_cmp_xy(z0, D.z1, D.n21, D.z1 * D.z1, C, [&] { return xy(1); });
+    dec.c2 = height_cmp_xy(z0, D.z2, D.n22, D.z2 * D.z2, C, [&] { return xy(2); });
+    if (dec.s2 == UNDECIDED || dec.d1 == UNDECIDED || dec.d2 == UNDECIDED ||
+        dec.c1 == UNDECIDED || dec.c2 == UNDECIDED) {
+      o.flags = F_NEEDEXACT;
+      return o;
+    }
+  }
+  const bool tangent = dec.s2 == 0;
+  o.flags = F_EXISTS | (tangent ? F_TANGENT : 0u) | (FORCED ? F_FALLBACK : 0u);
+  o.count = hit_rule(dec.d1, dec.d2, dec.c1, dec.c2, tangent, o.r0, o.r1);
+  return o;
+}
+
+// resolve_exact for a pair evaluated from its arc's record: s^2 and the heights from the
+// endpoints, the slope signs from the record.
+__host__ __device__ __forceinline__ bool resolve_exact_shared(Decisions& d, unsigned meta,
+                                                              double x1, double y1, double z1,
+                                                              double x2, double y2, double z2,
+                                                              double z0, double* arena) {
+  bool ok = true;
+  auto ex = [&](int which) {
+    int r = exact_sign(which, x1, y1, z1, x2, y2, z2, z0, arena);
+    if (r == 2) {
+      ok = false;
+      r = 0;
+    }
+    return r;
+  };
+  if (d.s2 == UNDECIDED) d.s2 = ex(PRED_S2);
+  if (d.d1 == UNDECIDED) {
+    d.d1 = arc_d(meta, ARC_D1_SHIFT);
+    if (meta & ARC_XOVER) ok = false;
+  }
+  if (d.d2 == UNDECIDED) {
+    d.d2 = arc_d(meta, ARC_D2_SHIFT);
+    if (meta & ARC_XOVER) ok = false;
+  }
+  if (d.c1 == UNDECIDED) d.c1 = sgn(z0) * ex(PRED_H1);
+  if (d.c2 == UNDECIDED) d.c2 = sgn(z0) * ex(PRED_H2);
+  return ok;
+}
+
 
 __host__ __device__ __forceinline__ PairOut eval_naive(bool valid, double x1, double y1,
                                                        double z1, double x2, double y2,

@@ -33,7 +33,8 @@ EXPORTS = ("sphint_arc_constlat", "sphint_workspace_size", "sphint_check",
            "sphint_batch_plan_create", "sphint_batch_autotune", "sphint_batch_launch",
            "sphint_batch_params", "sphint_batch_set_params", "sphint_batch_check",
            "sphint_plan_destroy", "sphint_batch_run_workspace_size", "sphint_batch_run",
-           "sphint_batch_scan", "sphint_batch_set_scan",
+           "sphint_batch_scan", "sphint_batch_set_scan", "sphint_batch_share",
+           "sphint_batch_set_share",
            "sphint_candidates_workspace_size", "sphint_candidates_count",
            "sphint_candidates_fill",
            "sphint_arc_arc",
@@ -111,6 +112,10 @@ def load():
     lib.sphint_batch_scan.restype = ctypes.c_int
     lib.sphint_batch_set_scan.argtypes = [vp, ctypes.c_int]
     lib.sphint_batch_set_scan.restype = ctypes.c_int
+    lib.sphint_batch_share.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.sphint_batch_share.restype = ctypes.c_int
+    lib.sphint_batch_set_share.argtypes = [vp, ctypes.c_int]
+    lib.sphint_batch_set_share.restype = ctypes.c_int
     lib.sphint_batch_check.argtypes = [vp]
     lib.sphint_batch_check.restype = ctypes.c_int
     lib.sphint_candidates_workspace_size.argtypes = [i64]
@@ -636,6 +641,16 @@ class BatchPlan:
 
     def set_lookback(self, on):
         _check(load().sphint_batch_set_scan(self.handle, 1 if on else 0), "sphint_batch_set_scan")
+
+    def share(self):
+        """True when an EFT plan over CSR lists shares arc records among a tile's rows."""
+        v = ctypes.c_int()
+        _check(load().sphint_batch_share(self.handle, ctypes.byref(v)), "sphint_batch_share")
+        return bool(v.value)
+
+    def set_share(self, on):
+        _check(load().sphint_batch_set_share(self.handle, 1 if on else 0),
+               "sphint_batch_set_share")
 
     def check(self):
         """Synchronises; raises if a kernel of the last launch reported an internal limit or

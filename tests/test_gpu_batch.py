@@ -3,7 +3,9 @@
 * One graph-replayed launch over all meshes gives, for every mesh, the bytes of a
   per-mesh sphint_arc_constlat call (counts, flags, hits), in both modes.
 * Every tile/schedule parameter choice the autotuner may pick (pairs per lane, workgroups
-  per CU, scanner or decoupled look-back) gives the same bytes.
+  per CU, scanner or decoupled look-back, and for EFT arc records shared by a tile's rows)
+  gives the same bytes, also on meshes with exact ties, degenerate and non-finite arcs,
+  out-of-range latitude indices and mostly empty candidate lists.
 * Graph replays, with eager work and synchronisations between them, all give the same
   bytes; the autotuner's cache file is written and read back.
 * One small mesh against the oracle.
@@ -122,13 +124,17 @@ def test_batch_equals_per_mesh(torch_cuda, mode, tmp_path):
         cache = os.path.join(str(tmp_path), "tune.txt")
         note(f"{mode}: autotune")
         plan.autotune(cache)
-        chosen = plan.params(), plan.lookback()
+        chosen = plan.params(), plan.lookback(), plan.share()
         assert chosen[0][0] in (1, 2, 3, 4) and chosen[0][1] >= 0
+        assert mode == "eft" or not chosen[2]
+        note(f"{mode}: autotuner chose {chosen}")
         assert os.path.exists(cache) and open(cache).read().strip()
         plan.set_params(1, 1)
         plan.set_lookback(not chosen[1])
+        if mode == "eft":
+            plan.set_share(not chosen[2])
         plan.autotune(cache)  # read back from the cache
-        assert (plan.params(), plan.lookback()) == chosen
+        assert (plan.params(), plan.lookback(), plan.share()) == chosen
         for rep in range(4):  # graph replays with eager work in between
             note(f"{mode}: replay {rep}")
             scrub(torch, devs)
@@ -242,3 +248,97 @@ def test_batch_run_equals_single_calls(torch_cuda, mode):
         got = read(d["out"])
         for key, v in ref[("dense", k)].items():
             assert np.array_equal(np.asarray(got[key]), np.asarray(v)), (k, key)
+
+
+class _Mesh:
+    """A CSR mesh from explicit arrays (the shape inputs.CsrMesh has)."""
+
+    def __init__(self, ends, lat_z, off, idx):
+        self.ends = [np.ascontiguousarray(a, dtype=np.float64) for a in ends]
+        self.lat_z = np.ascontiguousarray(lat_z, dtype=np.float64)
+        self.lat_offsets = np.ascontiguousarray(off, dtype=np.int64)
+        self.lat_idx = np.ascontiguousarray(idx, dtype=np.int32)
+        self.nnz = int(self.lat_offsets[-1])
+
+    def soa(self):
+        return self.ends
+
+
+def shared_arc_meshes():
+    """Meshes for the shared-arc schedules: uneven random meshes; one with many candidates
+    per arc (windows reused over many rows); one with most arcs without candidates (rows
+    spanning more than 64 arc ids: every lane computes its own arc); integer arcs with
+    latitudes at exact ties (open slope filters, the exact fallback); degenerate and
+    non-finite arcs with out-of-range latitude indices."""
+    import itertools
+    import math
+    import test_hostcheck_shared as TS
+    meshes = make_meshes(5, seed_tag=44)
+    meshes.append(inputs.random_mesh(inputs.rng(44, 50), 30_000, 3000))
+    meshes.append(inputs.random_mesh(inputs.rng(44, 51), 40_000, 12, d_hi=0.01))
+    verts = [v for v in itertools.product((-1.0, 0.0, 1.0), repeat=3) if any(v)]
+    zs = []
+    for z in (-1.0, -0.5, 0.0, 0.375, 1.0, 0.7071067811865476, 0.5773502691896258):
+        zs += [z, math.nextafter(z, 2.0), math.nextafter(z, -2.0)]
+    arcs = [(*a, *b) for a in verts for b in verts]
+    meshes.append(_Mesh(*TS._csr(arcs, [zs] * len(arcs))))
+    m = inputs.random_mesh(inputs.rng(44, 52), 3000, 200)
+    x1 = m.soa()[0].copy()
+    x1[::97] = np.inf
+    ends = [x1] + list(m.soa()[1:])
+    ends[3] = ends[3].copy()
+    ends[3][5::89] = ends[0][5::89]       # some arcs with equal endpoints (degenerate)
+    ends[4] = ends[4].copy()
+    ends[4][5::89] = ends[1][5::89]
+    ends[5] = ends[5].copy()
+    ends[5][5::89] = ends[2][5::89]
+    idx = m.lat_idx.copy()
+    idx[::11] = 10_000                    # out of range: NONFINITE, never an out-of-bounds read
+    meshes.append(_Mesh(ends, m.lat_z, m.lat_offsets, idx))
+    return meshes
+
+
+def test_batch_shared_arcs_equal_per_mesh(torch_cuda):
+    """EFT plans over CSR lists with arc records shared by a tile's rows: every schedule
+    (pairs per lane x scanner or look-back x workgroups per CU) gives, for every mesh, the
+    bytes of its single call; naive and dense plans refuse the option."""
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    meshes = shared_arc_meshes()
+    note(f"shared arcs: {len(meshes)} meshes, nnz {[m.nnz for m in meshes]}")
+    devs = [to_dev(torch, m) for m in meshes]
+    ref = per_mesh(torch, devs, "eft")
+    assert any(np.any(r["flags"] & 32) for r in ref)  # the exact fallback occurs
+    plan = sphint.BatchPlan(devs, mode="eft")
+    try:
+        assert not plan.share()
+        plan.set_share(True)
+        assert plan.share()
+        for lb in (False, True):
+            plan.set_lookback(lb)
+            for ppt in (1, 2, 3, 4):
+                for wg in (0, 1):
+                    note(f"shared arcs: ppt={ppt} wg_per_cu={wg} lookback={lb}")
+                    plan.set_params(ppt, wg)
+                    scrub(torch, devs)
+                    plan.launch()
+                    torch.cuda.synchronize()
+                    plan.check()
+                    for k, (d, r) in enumerate(zip(devs, ref)):
+                        assert same(read(d["out"]), r), (k, ppt, wg, lb)
+        for rep in range(3):  # graph replays
+            note(f"shared arcs: replay {rep}")
+            scrub(torch, devs)
+            plan.launch()
+            torch.cuda.synchronize()
+            plan.check()
+            for k, (d, r) in enumerate(zip(devs, ref)):
+                assert same(read(d["out"]), r), (k, rep)
+    finally:
+        plan.close()
+    naive = sphint.BatchPlan(devs[:2], mode="naive")
+    try:
+        with pytest.raises(sphint.SphintError):
+            naive.set_share(True)
+    finally:
+        naive.close()

@@ -171,6 +171,12 @@ def test_batch_rejects_bad_arguments():
     assert lib.sphint_batch_plan_create(arr, 1, 1, ctypes.byref(h)) == sphint.E_INVAL
     assert lib.sphint_batch_launch(None, None) == sphint.E_INVAL
     assert lib.sphint_set_profile_events(ctypes.c_void_p(1), None) == sphint.E_INVAL
+    v = ctypes.c_int()
+    assert lib.sphint_batch_scan(None, ctypes.byref(v)) == sphint.E_INVAL
+    assert lib.sphint_batch_set_scan(None, 0) == sphint.E_INVAL
+    assert lib.sphint_batch_share(None, ctypes.byref(v)) == sphint.E_INVAL
+    assert lib.sphint_batch_set_share(None, 1) == sphint.E_INVAL
+    assert lib.sphint_batch_set_params(None, 3, 0) == sphint.E_INVAL
 
 
 def _aa(**kw):
