@@ -31,7 +31,8 @@ BYTES_PER_HIT = 8 + 8 + 8 + 1  # x, y, pair, root
 # Algorithmic binary64 operations (add, sub, mul, FMA, and each sqrt or division, count 1),
 # counted on the operations the method defines (EFT: Alg. 8 with the normal renormalised,
 # plus the first stage of each exact-decision filter; naive: Eq. 2.2 and its predicates).
-EFT_OPS_PER_PAIR = 146 + 79      # per arc (normal, norms, F pairs, filter inputs) + per pair
+EFT_OPS_PER_ARC = 146            # normal, norms, F pairs, filter inputs (z0-free)
+EFT_OPS_PER_PAIR = EFT_OPS_PER_ARC + 79  # per arc part + per pair
 EFT_OPS_PER_HITPAIR = 16         # AccSqrt and the root-independent z0 products
 EFT_OPS_PER_HIT = 100            # two six-term CompDots and two divisions per root
 NAIVE_OPS_PER_PAIR = 25
@@ -124,12 +125,16 @@ def csr_main_bytes(arcs_used, nnz, n_lat, hits):
     return 48 * arcs_used + 10 * nnz + 8 * n_lat + BYTES_PER_HIT * hits
 
 
-def roofline(mode, r, pairs, bytes_launch, kernel, tag):
-    """Binding roof of the dominant kernel from its mean duration (HIP events)."""
+def roofline(mode, r, pairs, bytes_launch, kernel, tag, shared_arcs=None):
+    """Binding roof of the dominant kernel from its mean duration (HIP events).  With
+    shared_arcs (the number of arcs with candidates, when arc records are shared) the EFT
+    z0-free part counts once per arc instead of once per pair."""
     kms = statistics.mean(r["kernel_ms"])
     hits = r["total"]
     if mode == "eft":
-        ops_launch = EFT_OPS_PER_PAIR * pairs + EFT_OPS_PER_HITPAIR * r["hitpairs"] + EFT_OPS_PER_HIT * hits
+        per_arc = EFT_OPS_PER_ARC * (pairs if shared_arcs is None else shared_arcs)
+        ops_launch = (per_arc + (EFT_OPS_PER_PAIR - EFT_OPS_PER_ARC) * pairs
+                      + EFT_OPS_PER_HITPAIR * r["hitpairs"] + EFT_OPS_PER_HIT * hits)
     else:
         ops_launch = NAIVE_OPS_PER_PAIR * pairs + NAIVE_OPS_PER_HITPAIR * r["hitpairs"]
     bw = bytes_launch / (kms * 1e-3)
@@ -356,7 +361,10 @@ def batch_measure(torch, sphint, devs, stats, modes, steps, warmup):
                  f"{'true' if lb else 'false'},{'true' if share else 'false'}> with its init and "
                  f"pair-to-arc launches")
         roof = roofline(mode, {"kernel_ms": dms, "total": hits, "hitpairs": hitpairs}, nnz, byts,
-                        kname, None)
+                        kname, None, sum(st[1] for st in stats) if share else None)
+        if share:
+            roof["ops_note"] = ("arc records shared: the z0-free part of the EFT evaluation "
+                                "counts once per arc with candidates")
         res[mode] = dict(ms_per_step=t_batch * 1e3, device_ms=statistics.mean(dms),
                          per_mesh_ms=t_per * 1e3, speedup_vs_per_mesh=t_per / t_batch,
                          params=plan.params(), lookback=lb, share_arcs=share,
