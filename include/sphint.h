@@ -230,8 +230,9 @@ sphint_status sphint_batch_launch(sphint_plan *plan, void *stream);
  * since the grid's wavefronts must all be resident). */
 sphint_status sphint_batch_params(const sphint_plan *plan, int *pairs_per_thread,
                                   int *wg_per_cu);
-/* Sets the schedule by hand (pairs_per_thread 1 to 4; wg_per_cu >= 0, capped at what a CU
- * holds) instead of the autotuner's choice; the next launch re-captures the graph. */
+/* Sets the schedule by hand (pairs_per_thread 1 to 4, or 5 on a plan with shared arc
+ * records; wg_per_cu >= 0, capped at what a CU holds) instead of the autotuner's choice; the
+ * next launch re-captures the graph. */
 sphint_status sphint_batch_set_params(sphint_plan *plan, int pairs_per_thread, int wg_per_cu);
 /* How tiles learn their offsets in the compacted outputs: 0 = one scanner wavefront turns the
  * tiles' hit counts into prefixes in tile order; 1 = decoupled look-back (each wavefront sums
@@ -246,7 +247,8 @@ sphint_status sphint_batch_set_scan(sphint_plan *plan, int lookback);
  * consecutive arcs once, one arc per lane, and every pair of a tile row fetches its arc's
  * record from the lane holding it; 0 = every pair computes its arc's part (the single-call
  * path).  Results are identical, bit for bit.  SPHINT_E_INVAL for share = 1 on a naive or
- * dense plan.  Setting it re-captures the graph at the next launch. */
+ * dense plan, and for share = 0 while the plan has 5 pairs per thread (a shared-only tile
+ * size).  Setting it re-captures the graph at the next launch. */
 sphint_status sphint_batch_share(const sphint_plan *plan, int *share);
 sphint_status sphint_batch_set_share(sphint_plan *plan, int share);
 /* After the stream has completed a launch of the plan: SPHINT_E_DEVICE if a kernel of that

@@ -125,7 +125,9 @@ int resident_per_cu_form(sphint_mode mode, int ppt) {
   return max_resident<0, 4, CSR, LB>();
 }
 
-// Arc records are shared in EFT mode over CSR lists only.
+// Arc records are shared in EFT mode over CSR lists only; five pairs per lane exist with
+// them only.
+constexpr int PPT_SHARED_MAX = 5;
 bool can_share(const sphint_plan* p) { return p->mode == SPHINT_EFT_FP64 && p->csr; }
 
 void drop_graph(sphint_plan* p) {
@@ -178,7 +180,8 @@ int resident_per_cu_share(int ppt) {
   if (ppt == 1) return max_resident<1, 1, true, LB, true>();
   if (ppt == 2) return max_resident<1, 2, true, LB, true>();
   if (ppt == 3) return max_resident<1, 3, true, LB, true>();
-  return max_resident<1, 4, true, LB, true>();
+  if (ppt == 4) return max_resident<1, 4, true, LB, true>();
+  return max_resident<1, PPT_SHARED_MAX, true, LB, true>();
 }
 
 int resident_per_cu(const sphint_plan* p, int ppt, bool lb, bool share) {
@@ -201,6 +204,14 @@ void launch_batch_lb(const sphint_plan* p, unsigned grid, hipStream_t st) {
   else
     hipLaunchKernelGGL((k_batch<MODE, PPT, false, LB>), dim3(grid), dim3(BLOCK), 0, st, p->d_args,
                        p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
+}
+
+// Five-row tiles exist with shared arc records only (one window fill serves five rows; the
+// LDS already limits four-row EFT tiles to three workgroups per CU, and five still fit three).
+template <bool LB>
+void launch_batch_shared5(const sphint_plan* p, unsigned grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_batch<1, PPT_SHARED_MAX, true, LB, true>), dim3(grid), dim3(BLOCK), 0, st,
+                     p->d_args, p->d_tile_base, (int)p->meshes.size(), p->total_tiles);
 }
 
 template <int MODE, int PPT>
@@ -238,7 +249,9 @@ sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
     if (p->ppt == 1) eft ? launch_batch<1, 1>(p, (unsigned)grid, st) : launch_batch<0, 1>(p, (unsigned)grid, st);
     else if (p->ppt == 2) eft ? launch_batch<1, 2>(p, (unsigned)grid, st) : launch_batch<0, 2>(p, (unsigned)grid, st);
     else if (p->ppt == 3) eft ? launch_batch<1, 3>(p, (unsigned)grid, st) : launch_batch<0, 3>(p, (unsigned)grid, st);
-    else eft ? launch_batch<1, 4>(p, (unsigned)grid, st) : launch_batch<0, 4>(p, (unsigned)grid, st);
+    else if (p->ppt == 4) eft ? launch_batch<1, 4>(p, (unsigned)grid, st) : launch_batch<0, 4>(p, (unsigned)grid, st);
+    else if (p->lookback) launch_batch_shared5<true>(p, (unsigned)grid, st);  // shared only
+    else launch_batch_shared5<false>(p, (unsigned)grid, st);
   }
   if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
   return chain.end() == hipSuccess ? SPHINT_OK : SPHINT_E_HIP;
@@ -339,8 +352,9 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
         *bar = 0;
         if (key == line) {
           int ppt = 0, wg = -1, lb = 0, sh = 0;
-          if (sscanf(bar + 1, "%d %d %d %d", &ppt, &wg, &lb, &sh) >= 2 && (ppt >= 1 && ppt <= 4) &&
-              wg >= 0 && (lb == 0 || lb == 1) && (sh == 0 || (sh == 1 && can_share(p)))) {
+          if (sscanf(bar + 1, "%d %d %d %d", &ppt, &wg, &lb, &sh) >= 2 && ppt >= 1 &&
+              (ppt <= 4 || (ppt == PPT_SHARED_MAX && sh == 1)) && wg >= 0 &&
+              (lb == 0 || lb == 1) && (sh == 0 || (sh == 1 && can_share(p)))) {
             fclose(f);
             p->ppt = ppt;
             p->wg_per_cu = wg;
@@ -366,13 +380,21 @@ extern "C" sphint_status sphint_batch_autotune(sphint_plan* p, const char* cache
   float best = 1e30f;
   int best_ppt = 1, best_wg = 0;
   bool best_lb = false, best_share = false;
-  const int ppts[4] = {1, 2, 3, 4};
-  const int ncand = can_share(p) ? 16 : 8;
-  for (int ci = 0; ci < ncand; ++ci) {
-    const bool lb = (ci & 4) != 0;
-    const bool share = ci >= 8;
-    const int ppt = ppts[ci & 3];
-    if (share && ppt == 1) continue;  // one-row tiles share nothing across rows
+  // candidates: pairs per lane 1-4 x {scanner, look-back}; with shared arc records (EFT over
+  // CSR lists) also pairs per lane 2-5 (one-row tiles share nothing across rows)
+  struct Cand {
+    int ppt;
+    bool lb, share;
+  };
+  std::vector<Cand> cands;
+  for (int lb = 0; lb < 2; ++lb)
+    for (int ppt = 1; ppt <= 4; ++ppt) cands.push_back({ppt, lb == 1, false});
+  if (can_share(p))
+    for (int lb = 0; lb < 2; ++lb)
+      for (int ppt = 2; ppt <= PPT_SHARED_MAX; ++ppt) cands.push_back({ppt, lb == 1, true});
+  for (const Cand& c : cands) {
+    const int ppt = c.ppt;
+    const bool lb = c.lb, share = c.share;
     const int res = resident_per_cu(p, ppt, lb, share);
     const int wgs[4] = {res, res > 1 ? res - 1 : 1, res > 2 ? res / 2 : 1, 1};
     for (int wi = 0; wi < 4; ++wi) {
@@ -426,8 +448,8 @@ extern "C" sphint_status sphint_batch_params(const sphint_plan* p, int* pairs_pe
 
 extern "C" sphint_status sphint_batch_set_params(sphint_plan* p, int pairs_per_thread,
                                                  int wg_per_cu) {
-  if (!p || pairs_per_thread < 1 || pairs_per_thread > 4 ||
-      wg_per_cu < 0)
+  if (!p || pairs_per_thread < 1 || wg_per_cu < 0 ||
+      pairs_per_thread > (p->share ? PPT_SHARED_MAX : 4))
     return SPHINT_E_INVAL;
   p->ppt = pairs_per_thread;
   p->wg_per_cu = wg_per_cu;
@@ -453,7 +475,9 @@ extern "C" sphint_status sphint_batch_share(const sphint_plan* p, int* share) {
 }
 
 extern "C" sphint_status sphint_batch_set_share(sphint_plan* p, int share) {
-  if (!p || (share != 0 && share != 1) || (share == 1 && !can_share(p))) return SPHINT_E_INVAL;
+  if (!p || (share != 0 && share != 1) || (share == 1 && !can_share(p)) ||
+      (share == 0 && p->ppt > 4))
+    return SPHINT_E_INVAL;
   p->share = share == 1;
   return layout(p);
 }

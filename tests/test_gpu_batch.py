@@ -316,7 +316,7 @@ def test_batch_shared_arcs_equal_per_mesh(torch_cuda):
         assert plan.share()
         for lb in (False, True):
             plan.set_lookback(lb)
-            for ppt in (1, 2, 3, 4):
+            for ppt in (1, 2, 3, 4, 5):
                 for wg in (0, 1):
                     note(f"shared arcs: ppt={ppt} wg_per_cu={wg} lookback={lb}")
                     plan.set_params(ppt, wg)
@@ -334,6 +334,12 @@ def test_batch_shared_arcs_equal_per_mesh(torch_cuda):
             plan.check()
             for k, (d, r) in enumerate(zip(devs, ref)):
                 assert same(read(d["out"]), r), (k, rep)
+        with pytest.raises(sphint.SphintError):
+            plan.set_share(False)  # five pairs per lane exist with shared records only
+        plan.set_params(4, 0)
+        plan.set_share(False)
+        with pytest.raises(sphint.SphintError):
+            plan.set_params(5, 0)
     finally:
         plan.close()
     naive = sphint.BatchPlan(devs[:2], mode="naive")
