@@ -42,6 +42,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   const int64_t gw = (int64_t)blockIdx.x * NWAVE + wave;
   const int64_t W = (int64_t)gridDim.x * NWAVE - (LB ? 0 : 1);
   if (!LB && gw == W) {  // the scanner follows the global tile order: mesh after mesh
+    __builtin_amdgcn_s_setprio(3);  // ahead of the compute wavefronts on its SIMD
     for (int m = 0; m < n_meshes; ++m) {
       const KArgs a = args[m];
       scan_tiles<scan_k<PPT>()>(a.status, a.ntiles, a.ototal, a.ws, a.wait_ticks,

@@ -777,6 +777,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   const int64_t gw = (int64_t)blockIdx.x * NWAVE + wave;
   const int64_t W = (int64_t)gridDim.x * NWAVE - 1;
   if (gw == W) {
+    // The scanner shares its SIMD with compute wavefronts; at the default priority it gets
+    // a fraction of the issue slots and every tile's prefix waits on it.
+    __builtin_amdgcn_s_setprio(3);
     scan_tiles<scan_k<WPPT>()>(a.status, a.ntiles, a.ototal, a.ws, a.wait_ticks,
                                reinterpret_cast<uint64_t*>(&sh.stage[wave]));
     return;
