@@ -94,9 +94,26 @@ def measured_valu(kernel_tag, digest):
         return None
 
 
-def run_mode(torch, sphint, call, nnz, mode, steps, warmup):
-    """Times `steps` calls of call(out, mode) (one sphint_arc_constlat each)."""
+def settle(torch, call, out, mode, seconds):
+    """Untimed calls of the mode for `seconds` of wall time, before the warm-up steps.  Under
+    sustained binary64 load the GPU's clock settles over the first ~0.1 s: the first calls
+    of a fresh process run up to ~20% slower than the steady state that the timed steps are
+    meant to measure.  Returns the number of calls made."""
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            call(out, mode)
+        torch.cuda.synchronize()
+        n += 10
+    return n
+
+
+def run_mode(torch, sphint, call, nnz, mode, steps, warmup, settle_s=0.0):
+    """Times `steps` calls of call(out, mode) (one sphint_arc_constlat each), after
+    settle_s seconds of untimed calls and `warmup` untimed steps."""
     out = sphint.Output(nnz)
+    settled = settle(torch, call, out, mode, settle_s) if settle_s > 0 else 0
     for _ in range(warmup):
         call(out, mode)
     total = out.check()
@@ -114,7 +131,8 @@ def run_mode(torch, sphint, call, nnz, mode, steps, warmup):
     total2 = out.check()
     assert total2 == total
     hitpairs = int((out.count > 0).sum().item())  # accounting only, after the timed region
-    return dict(wall_s=t1 - t0, kernel_ms=kms, total=total, hitpairs=hitpairs, out=out)
+    return dict(wall_s=t1 - t0, kernel_ms=kms, total=total, hitpairs=hitpairs, out=out,
+                settle_calls=settled)
 
 
 def csr_main_bytes(arcs_used, nnz, n_lat, hits):
@@ -275,7 +293,7 @@ def candidate_timing(torch, sphint, inputs, mesh, dp, lz, reps=10):
             "arcs_per_s_gpu": len(mesh.p1) / gpu_s}
 
 
-def cubed_subresult(torch, np, sphint, inputs, steps, warmup):
+def cubed_subresult(torch, np, sphint, inputs, steps, warmup, settle_s=0.0):
     """The regridding-shaped workload (ne = 1024 cubed sphere x 1800 latitudes, CSR) in both
     modes: wall time per call, main-kernel time (HIP events) and its roofline."""
     log("[bench] cubed sphere ne=1024 x 1800 latitudes: generating")
@@ -291,7 +309,7 @@ def cubed_subresult(torch, np, sphint, inputs, steps, warmup):
                        "latitude lines (-89.95 deg + 0.1 deg k), CSR candidates from z-range "
                        "overlap", "pairs": n, "arcs": mesh.n_arcs, "arcs_with_candidates": arcs_used}
     for mode in ("eft", "naive"):
-        r = run_mode(torch, sphint, call, n, mode, steps, warmup)
+        r = run_mode(torch, sphint, call, n, mode, steps, warmup, settle_s)
         byts = csr_main_bytes(arcs_used, n, len(mesh.lat_z), r["total"])
         kern = f"sphint::k_intersect_w<{1 if mode == 'eft' else 0},{3 if mode == 'eft' else 4},true>"
         roof = roofline(mode, r, n, byts, kern, f"k_intersect_w_{mode}_cubed1024")
@@ -515,6 +533,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--settle", type=float, default=0.2,
+                    help="seconds of untimed calls per mode before the warm-up steps (the GPU "
+                         "clock settles under sustained load)")
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--workload", default="ill1e7",
                     choices=["ill1e7", "cubed1024", "batch64", "arcarc1e7", "adaptive",
@@ -600,11 +621,11 @@ def main():
 
     res = {}
     for mode in args.modes.split(","):
-        log(f"[bench] mode={mode} warmup={args.warmup} steps={args.steps}")
-        res[mode] = run_mode(torch, sphint, call, n, mode, args.steps, args.warmup)
+        log(f"[bench] mode={mode} settle={args.settle}s warmup={args.warmup} steps={args.steps}")
+        res[mode] = run_mode(torch, sphint, call, n, mode, args.steps, args.warmup, args.settle)
         r = res[mode]
         log(f"[bench] mode={mode} wall={r['wall_s']:.4f}s kernel_mean={statistics.mean(r['kernel_ms']):.4f}ms "
-            f"hits={r['total']}")
+            f"hits={r['total']} settle_calls={r['settle_calls']}")
 
     copy_calibration(torch, args.copy_calibration)
 
@@ -625,6 +646,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle": {"seconds": args.settle, "calls": r["settle_calls"],
+                   "note": "untimed calls of the same mode before the warm-up steps"},
         "ms_per_step": r["wall_s"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -649,7 +672,7 @@ def main():
     if not args.no_serve and args.workload == "ill1e7":
         line["serving"] = serving(torch, args, log)
     if not args.no_subresults and args.workload == "ill1e7":
-        line["cubed_sphere"] = cubed_subresult(torch, np, sphint, inputs, 10, 3)
+        line["cubed_sphere"] = cubed_subresult(torch, np, sphint, inputs, 10, 3, args.settle)
         line["batch64"] = batch_subresult(torch, sphint, inputs, 5, 2)
     if args.workload == "cubed1024":
         log("[bench] candidate lists on the GPU and on the host")
