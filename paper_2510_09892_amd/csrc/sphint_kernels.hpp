@@ -272,8 +272,7 @@ template <int WPPT>
 struct WaveStage {
   double x[2 * 64 * WPPT];
   double y[2 * 64 * WPPT];
-  uint16_t pair[2 * 64 * WPPT];  // pair offset within the tile
-  uint8_t root[2 * 64 * WPPT];
+  uint16_t pair[2 * 64 * WPPT];  // pair offset within the tile (bits 0-9), root (bit 15)
 };
 
 // Tiles per scanner lane per pass: the scanner borrows its own (unused) staging buffer.
@@ -624,14 +623,12 @@ __device__ __forceinline__ void stage_row(const TileRegs<WPPT>& r, int j, WaveSt
   if (o.count >= 1) {
     st.x[p] = o.px0;
     st.y[p] = o.py0;
-    st.pair[p] = off;
-    st.root[p] = (uint8_t)o.r0;
+    st.pair[p] = (uint16_t)(off | (o.r0 << 15));
   }
   if (o.count >= 2) {
     st.x[p + 1] = o.px1;
     st.y[p + 1] = o.py1;
-    st.pair[p + 1] = off;
-    st.root[p + 1] = (uint8_t)o.r1;
+    st.pair[p + 1] = (uint16_t)(off | (o.r1 << 15));
   }
 }
 
@@ -653,8 +650,9 @@ __device__ __forceinline__ void flush_tile(const KArgs& a, int64_t tile, int cou
     const uint32_t kk = (uint32_t)k & 2047u;
     gptr(ox)[kk] = st.x[kk];
     gptr(oy)[kk] = st.y[kk];
-    gptr(op)[kk] = base + st.pair[kk];
-    gptr(orr)[kk] = st.root[kk];
+    const uint32_t w = st.pair[kk];
+    gptr(op)[kk] = base + (w & 1023u);
+    gptr(orr)[kk] = (uint8_t)(w >> 15);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

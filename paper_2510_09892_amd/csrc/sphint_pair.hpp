@@ -338,17 +338,19 @@ __host__ __device__ __forceinline__ void points_eft_g(G&& g, double S2, double z
   const bool plus0 = o.r0 == ROOT_PLUS;
   const double sb = plus0 ? sq.hi : -sq.hi;
   const double es = plus0 ? sq.lo : -sq.lo;
-  const double ny = g(6), eny = g(7);
-  const dd x2 = two_prod(ny, sb), x3 = two_prod(eny, sb);
-  const dd x4 = two_prod(ny, es), x5 = two_prod(eny, es);
-  const double nx = g(4), enx = g(5);
-  const dd y2 = two_prod(-nx, sb), y3 = two_prod(-enx, sb);
-  const dd y4 = two_prod(-nx, es), y5 = two_prod(-enx, es);
-  o.px0 = -(comp_dot_tail(hx, x2, x3, x4, x5, 1.0) / S2);
-  o.py0 = -(comp_dot_tail(hy, y2, y3, y4, y5, 1.0) / S2);
-  if (o.count == 2) {
-    o.px1 = -(comp_dot_tail(hx, x2, x3, x4, x5, -1.0) / S2);
-    o.py1 = -(comp_dot_tail(hy, y2, y3, y4, y5, -1.0) / S2);
+  {  // x of both roots, then y: the eight TwoProducts of one coordinate live at a time
+    const double ny = g(6), eny = g(7);
+    const dd x2 = two_prod(ny, sb), x3 = two_prod(eny, sb);
+    const dd x4 = two_prod(ny, es), x5 = two_prod(eny, es);
+    o.px0 = -(comp_dot_tail(hx, x2, x3, x4, x5, 1.0) / S2);
+    if (o.count == 2) o.px1 = -(comp_dot_tail(hx, x2, x3, x4, x5, -1.0) / S2);
+  }
+  {
+    const double nx = g(4), enx = g(5);
+    const dd y2 = two_prod(-nx, sb), y3 = two_prod(-enx, sb);
+    const dd y4 = two_prod(-nx, es), y5 = two_prod(-enx, es);
+    o.py0 = -(comp_dot_tail(hy, y2, y3, y4, y5, 1.0) / S2);
+    if (o.count == 2) o.py1 = -(comp_dot_tail(hy, y2, y3, y4, y5, -1.0) / S2);
   }
 }
 
