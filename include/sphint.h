@@ -114,6 +114,10 @@ typedef struct {
  * out_total   one int64 (device): total hits of this call.
  * workspace   device memory of at least sphint_workspace_size(nnz) bytes, 256-byte
  *             aligned, used only by this call while it runs.
+ * EFT calls in the CSR form with at least 2.5 candidates per arc on average
+ * (2 * nnz >= 5 * n_arcs) evaluate each arc's z0-free part (Alg. 8's normal, norms and F
+ * pairs, and the containment rule's slope signs) once per tile row window and share it
+ * among the arc's candidates; the results are the same bytes either way.
  * Returns SPHINT_E_INVAL (no launch) for negative sizes, missing pointers, mismatched
  * dense sizes, n_arcs >= 2^32 in the CSR form, nnz > 2^40 or more than 2^31 - 1 tiles of
  * 192 (EFT) or 256 (naive) pairs, or a short workspace; SPHINT_E_HIP if a launch fails;

@@ -68,31 +68,38 @@ constexpr int wppt_single() {
 constexpr int WG_PER_CU_SINGLE = 4;  // resident workgroups per CU of the persistent grid
 
 
-// Workgroups of k_intersect_w<MODE, wppt_single<MODE>(), CSR> one CU holds at once
+// EFT calls over CSR lists share each arc's z0-free part among the arc's candidates (arc
+// records in registers, as the batched kernel's shared schedules) when the lists hold at
+// least 2.5 candidates per arc on average; sparser lists (the cubed sphere holds 0.48) keep
+// the per-pair evaluation, since a row then spans more arcs than a window holds.  Results
+// are the same either way.
+inline bool share_arcs(int64_t nnz, int64_t n_arcs) { return 2 * nnz >= 5 * n_arcs; }
+
+// Workgroups of k_intersect_w<MODE, wppt_single<MODE>(), CSR, SHARE> one CU holds at once
 // (queried once).
-template <int MODE, bool CSR>
+template <int MODE, bool CSR, bool SHARE>
 int resident_per_cu() {
   static std::atomic<int> cached{0};  // calls may come from several host threads
   int b = cached.load(std::memory_order_relaxed);
   if (!b) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_intersect_w<MODE, wppt_single<MODE>(), CSR>,
-                                                     BLOCK, 0) != hipSuccess || b <= 0)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &b, k_intersect_w<MODE, wppt_single<MODE>(), CSR, SHARE>, BLOCK, 0) != hipSuccess ||
+        b <= 0)
       b = 1;
     cached.store(b, std::memory_order_relaxed);
   }
   return b;
 }
 
-template <int MODE, bool CSR>
+template <int MODE, bool CSR, bool SHARE = false>
 hipError_t launch_main(const KArgs& k, hipStream_t st) {
-  int per_cu = resident_per_cu<MODE, CSR>();
+  int per_cu = resident_per_cu<MODE, CSR, SHARE>();
   if (per_cu > WG_PER_CU_SINGLE) per_cu = WG_PER_CU_SINGLE;
   int64_t grid = (int64_t)per_cu * device_cus();
   const int64_t need = (k.ntiles + 1 + NWAVE - 1) / NWAVE;  // + the scanner wavefront
   if (grid > need) grid = need;
-  hipLaunchKernelGGL((k_intersect_w<MODE, wppt_single<MODE>(), CSR>), dim3((unsigned)grid),
-                     dim3(BLOCK), 0,
-                     st, k);
+  hipLaunchKernelGGL((k_intersect_w<MODE, wppt_single<MODE>(), CSR, SHARE>), dim3((unsigned)grid),
+                     dim3(BLOCK), 0, st, k);
   return hipGetLastError();
 }
 
@@ -132,7 +139,9 @@ static sphint_status arc_constlat_on(int64_t n_arcs, const sphint_pts_soa& p1,
       return SPHINT_E_HIP;
     const bool csr = lat_offsets != nullptr;
     if (mode == SPHINT_EFT_FP64)
-      e = csr ? launch_main<1, true>(k, st) : launch_main<1, false>(k, st);
+      e = !csr ? launch_main<1, false>(k, st)
+          : share_arcs(nnz, n_arcs) ? launch_main<1, true, true>(k, st)
+                                    : launch_main<1, true>(k, st);
     else
       e = csr ? launch_main<0, true>(k, st) : launch_main<0, false>(k, st);
     if (e == hipSuccess && profile_events().stop) e = hipEventRecord(profile_events().stop, st);

@@ -766,7 +766,7 @@ constexpr int flush_at() {
 // atomic tile counter (a single contended address serialises at tens of millions of
 // operations per second).  The last wavefront of the grid is the scanner; compute wavefront
 // c of the other W takes tiles c, c + W, c + 2W, ...
-template <int MODE, int WPPT, bool CSR>
+template <int MODE, int WPPT, bool CSR, bool SHARE = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_intersect_w(KArgs a) {
   __shared__ WgShared<MODE, WPPT, CSR> sh;
   if (threadIdx.x == 0) sh.lock = 0;
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     return;
   }
   int64_t t = gw;
-  wave_loop<MODE, WPPT, CSR, flush_at<MODE, WPPT>(), false>(&a, sh, [&](int& m, int64_t& tile) {
+  wave_loop<MODE, WPPT, CSR, flush_at<MODE, WPPT>(), false, SHARE>(&a, sh, [&](int& m, int64_t& tile) {
     if (t >= a.ntiles) return false;
     m = 0;
     tile = t;

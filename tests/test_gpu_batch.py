@@ -300,18 +300,28 @@ def shared_arc_meshes():
 
 def test_batch_shared_arcs_equal_per_mesh(torch_cuda):
     """EFT plans over CSR lists with arc records shared by a tile's rows: every schedule
-    (pairs per lane x scanner or look-back x workgroups per CU) gives, for every mesh, the
-    bytes of its single call; naive and dense plans refuse the option."""
+    (pairs per lane x scanner or look-back x workgroups per CU), and every single call, gives
+    for every mesh the bytes of the per-pair schedule; naive and dense plans refuse the
+    option."""
     from paper_2510_09892_amd import sphint
     torch = torch_cuda
     meshes = shared_arc_meshes()
     note(f"shared arcs: {len(meshes)} meshes, nnz {[m.nnz for m in meshes]}")
     devs = [to_dev(torch, m) for m in meshes]
-    ref = per_mesh(torch, devs, "eft")
-    assert any(np.any(r["flags"] & 32) for r in ref)  # the exact fallback occurs
     plan = sphint.BatchPlan(devs, mode="eft")
     try:
         assert not plan.share()
+        # the reference: every pair evaluated from its own endpoints (per-pair schedule)
+        plan.set_params(3, 0)
+        scrub(torch, devs)
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.check()
+        ref = [read(d["out"]) for d in devs]
+        assert any(np.any(r["flags"] & 32) for r in ref)  # the exact fallback occurs
+        # single calls (which share arc records on meshes with >= 2.5 candidates per arc)
+        for k, (r, s) in enumerate(zip(ref, per_mesh(torch, devs, "eft"))):
+            assert same(s, r), k
         plan.set_share(True)
         assert plan.share()
         for lb in (False, True):

@@ -234,6 +234,31 @@ def test_csr_run_shapes(torch_cuda, mode):
     (check_eft if mode == "eft" else check_naive)(res, m.expand().soa())
 
 
+def test_csr_dense_candidates_shared_arcs(torch_cuda):
+    """CSR EFT calls with many candidates per arc take the shared-arc path (each arc's
+    z0-free part computed once and fetched by the arc's candidates): against the oracle on
+    a random mesh, and on integer arcs whose slope and height decisions are exact ties
+    (open slope filters resolved per arc, the exact fallback per pair)."""
+    import itertools
+    import test_hostcheck_shared as TS
+    m = inputs.random_mesh(inputs.rng(110), 700, 3000, d_hi=0.05)
+    assert 2 * m.nnz >= 5 * m.n_arcs  # the library's threshold for sharing
+    note(f"csr dense candidates eft arcs={m.n_arcs} nnz={m.nnz}")
+    check_eft(gpu_csr(torch_cuda, m, "eft"), m.expand().soa())
+    verts = [v for v in itertools.product((-1.0, 0.0, 1.0), repeat=3) if any(v)]
+    zs = []
+    for z in (-1.0, -0.5, 0.0, 0.375, 1.0, 0.7071067811865476, 0.5773502691896258):
+        zs += [z, math.nextafter(z, 2.0), math.nextafter(z, -2.0)]
+    ends, table, off, idx = TS._csr([(*a, *b) for a in verts for b in verts],
+                                    [zs] * (len(verts) ** 2))
+    t = inputs.CsrMesh(np.stack(ends[:3], 1), np.stack(ends[3:], 1), table, off, idx)
+    assert 2 * t.nnz >= 5 * t.n_arcs
+    note(f"csr exact-tie mesh eft arcs={t.n_arcs} nnz={t.nnz}")
+    res = gpu_csr(torch_cuda, t, "eft")
+    assert np.any(res["flags"] & 32)  # the exact fallback ran
+    check_eft(res, t.expand().soa())
+
+
 def test_csr_bad_latitude_index_is_flagged(torch_cuda):
     m = inputs.random_mesh(inputs.rng(108), 200, 50)
     m.lat_idx[::7] = 10_000          # out of range: must become NONFINITE, not an OOB read
