@@ -311,7 +311,9 @@ def cubed_subresult(torch, np, sphint, inputs, steps, warmup, settle_s=0.0):
     for mode in ("eft", "naive"):
         r = run_mode(torch, sphint, call, n, mode, steps, warmup, settle_s)
         byts = csr_main_bytes(arcs_used, n, len(mesh.lat_z), r["total"])
-        kern = f"sphint::k_intersect_w<{1 if mode == 'eft' else 0},{3 if mode == 'eft' else 4},true>"
+        shared = mode == "eft" and 2 * n >= 5 * mesh.n_arcs  # the rule sphint_arc_constlat applies
+        kern = (f"sphint::k_intersect_w<{1 if mode == 'eft' else 0},{3 if mode == 'eft' else 4},"
+                f"true,{'true' if shared else 'false'}>")
         roof = roofline(mode, r, n, byts, kern, f"k_intersect_w_{mode}_cubed1024")
         if roof.get("traffic"):
             roof["traffic_over_algorithmic"] = roof["traffic"] / byts
@@ -634,7 +636,8 @@ def main():
     value = n * args.steps / r["wall_s"]
     hits = r["total"]
     kname = lambda m: (f"sphint::k_intersect_w<{1 if m == 'eft' else 0},{3 if m == 'eft' else 4},"
-                       f"{'true' if csr else 'false'}>")
+                       f"{'true' if csr else 'false'},"
+                       f"{'true' if m == 'eft' and csr and 2 * n >= 5 * mesh.n_arcs else 'false'}>")
     kernel = kname(head)
     tag = f"k_intersect_w_{head}_{args.workload}"
     roof = roofline(head, r, n, bytes_in + BYTES_PER_HIT * hits, kernel, tag)
