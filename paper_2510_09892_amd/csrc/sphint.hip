@@ -42,23 +42,8 @@ __global__ __launch_bounds__(64) void k_error_out(const uint32_t* ws, int32_t* o
   if (threadIdx.x == 0) *out_error = (int32_t)ws[1];
 }
 
-}  // namespace
-
-namespace sphint {
-__global__ __launch_bounds__(INIT_BLOCK) void k_pair_arcs(const int64_t* __restrict__ off,
-                                                          int64_t n_arcs, int64_t nnz,
-                                                          uint32_t* __restrict__ parc) {
-  __shared__ uint32_t win[INIT_BLOCK / 64][FILL_W];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  fill_pair_arcs(off, n_arcs, nnz, parc, (int64_t)blockIdx.x * (INIT_BLOCK / 64) + wave,
-                 (int64_t)gridDim.x * (INIT_BLOCK / 64), win[wave]);
-}
-}  // namespace sphint
-
-namespace {
-
 // Pairs per lane of single calls: the EFT evaluation is compute-heavy and gains from four
-// resident waves per SIMD, which its 3-row tiles (192 pairs, 29-33 KB of LDS per
+// resident waves per SIMD, which its 3-row tiles (192 pairs, 31.75 KB of LDS per
 // workgroup) allow; the memory-bound naive evaluation does better with fewer, larger
 // 4-row tiles (256 pairs).
 template <int MODE>

@@ -62,8 +62,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   });
 }
 
-__global__ void k_batch_init(uint32_t* ws, uint64_t* status, int64_t total_tiles,
-                             const KArgs* __restrict__ args, int n_meshes) {
+// Clears the header and tile states, zeroes the totals of empty meshes and, for CSR plans,
+// fills every mesh's pair-to-arc table in the same launch (every wavefront takes part in
+// every mesh's fill, as in the one-shot launch's init).
+__global__ __launch_bounds__(INIT_BLOCK) void k_batch_init(uint32_t* ws, uint64_t* status,
+                                                           int64_t total_tiles,
+                                                           const KArgs* __restrict__ args,
+                                                           int n_meshes, int csr) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     ws[0] = 0u;
@@ -71,6 +76,16 @@ __global__ void k_batch_init(uint32_t* ws, uint64_t* status, int64_t total_tiles
   }
   if (t < n_meshes && args[t].nnz == 0) *args[t].ototal = 0;
   for (int64_t k = t; k < total_tiles; k += (int64_t)gridDim.x * blockDim.x) status[k] = 0ull;
+  if (!csr) return;
+  __shared__ uint32_t win[INIT_BLOCK / 64][FILL_W];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int m = 0; m < n_meshes; ++m) {
+    const KArgs& a = args[m];
+    if (a.nnz > 0)
+      fill_pair_arcs(a.off, a.n_arcs, a.nnz, const_cast<uint32_t*>(a.parc),
+                     (int64_t)blockIdx.x * (INIT_BLOCK / 64) + wave,
+                     (int64_t)gridDim.x * (INIT_BLOCK / 64), win[wave]);
+  }
 }
 
 struct sphint_plan {
@@ -89,7 +104,6 @@ struct sphint_plan {
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   std::vector<int64_t> tile_base;
-  std::vector<uint32_t*> parc;  // CSR: each mesh's pair-to-arc table in d_ws
   int64_t total_tiles = 0;
   bool csr = false;  // every mesh of a plan has the same form
   hipStream_t capture_stream = nullptr;
@@ -159,10 +173,8 @@ sphint_status layout(sphint_plan* p) {
   uint64_t* status = (uint64_t*)((char*)p->d_ws + WS_HEADER);
   uint32_t* parc = (uint32_t*)((char*)p->d_ws + WS_HEADER + 8 * status_words);
   std::vector<KArgs> h(n);
-  p->parc.assign(n, nullptr);
   for (int m = 0; m < n; ++m) {
     const sphint_mesh_desc& d = p->meshes[m];
-    p->parc[m] = p->csr ? parc : nullptr;
     h[m] = make_args(d.n_arcs, d.p1, d.p2, d.lat_z, d.n_lat, d.lat_offsets, d.lat_idx, d.nnz,
                      d.out, d.out_count, d.out_flags, d.out_total, ws,
                      status + p->tile_base[m], p->tile_base[m + 1] - p->tile_base[m], parc);
@@ -229,17 +241,16 @@ sphint_status enqueue(const sphint_plan* p, hipStream_t st) {
   uint64_t* status = (uint64_t*)((char*)p->d_ws + WS_HEADER);
   const int n = (int)p->meshes.size();
   int64_t work = p->total_tiles > n ? p->total_tiles : n;
-  unsigned ib = (unsigned)((work + 255) / 256);
+  int64_t ib = (work + INIT_BLOCK - 1) / INIT_BLOCK;
   if (ib > 1024) ib = 1024;
-  if (ib == 0) ib = 1;
-  hipLaunchKernelGGL(k_batch_init, dim3(ib), dim3(256), 0, st, ws, status, p->total_tiles,
-                     p->d_args, n);
   if (p->csr)
-    for (int m = 0; m < n; ++m) {
-      const sphint_mesh_desc& d = p->meshes[m];
-      if (launch_pair_arcs(d.lat_offsets, d.n_arcs, d.nnz, p->parc[m], st) != hipSuccess)
-        return SPHINT_E_HIP;
-    }
+    for (int m = 0; m < n; ++m)
+      if (p->meshes[m].nnz > 0 && fill_blocks(p->meshes[m].n_arcs) > ib)
+        ib = fill_blocks(p->meshes[m].n_arcs);
+  if (ib < 1) ib = 1;
+  hipLaunchKernelGGL(k_batch_init, dim3((unsigned)ib), dim3(INIT_BLOCK), 0, st, ws, status,
+                     p->total_tiles, p->d_args, n, p->csr ? 1 : 0);
+  if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
   if (p->total_tiles > 0) {
     // every wavefront of the grid must be resident at once (see k_batch)
     const int res = resident_per_cu(p, p->ppt, p->lookback, p->share);

@@ -71,18 +71,6 @@ inline int64_t fill_blocks(int64_t n_arcs) {
   return b > 8192 ? 8192 : (b < 1 ? 1 : b);
 }
 
-// The CSR pair-to-arc table (fill_pair_arcs) as a launch of its own.
-__global__ void k_pair_arcs(const int64_t* __restrict__ off, int64_t n_arcs, int64_t nnz,
-                            uint32_t* __restrict__ parc);
-
-inline hipError_t launch_pair_arcs(const int64_t* off, int64_t n_arcs, int64_t nnz,
-                                   uint32_t* parc, hipStream_t st) {
-  if (n_arcs <= 0 || nnz <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pair_arcs, dim3((unsigned)fill_blocks(n_arcs)), dim3(INIT_BLOCK), 0, st,
-                     off, n_arcs, nnz, parc);
-  return hipGetLastError();
-}
-
 // Argument checks shared by the single-call and batched paths.
 inline sphint_status validate(int64_t n_arcs, const sphint_pts_soa& p1, const sphint_pts_soa& p2,
                               const double* lat_z, int64_t n_lat, const int64_t* off,

@@ -333,7 +333,7 @@ __device__ __forceinline__ TileCtx tile_ctx(const KArgs& a, int64_t tile) {
 // Loads one row without branches: lanes past the end read the last pair (and are marked
 // invalid), so the compiler can count outstanding loads exactly and the row fetched ahead
 // stays in flight while the current row is evaluated.  CSR calls take each pair's arc from
-// the pair-to-arc table that k_pair_arcs wrote (clamped, so malformed offsets cannot send
+// the pair-to-arc table that the init launch wrote (clamped, so malformed offsets cannot send
 // a read out of bounds).
 template <bool CSR, bool SHARE = false>
 __device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int j) {
