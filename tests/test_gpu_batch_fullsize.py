@@ -7,7 +7,9 @@ the library's own candidate kernels, so the whole set is ready in seconds; the b
 host-built lists differ only by extra edge candidates.  Checks, in the benchmark's launch
 configuration (one autotuned persistent graph launch):
 
-* every mesh's output equals that mesh's single call bit for bit (compared on the device);
+* every mesh's output equals that mesh's single call bit for bit (compared on the device),
+  and in EFT mode also the per-pair schedule's (the autotuned launch and the single calls
+  share arc records on dense candidate lists);
 * 400 pairs sampled across the meshes match the exact oracle (counts, roots, flags) and the
   AccuX replica (points, within 4 * 2^-53).
 """
@@ -85,6 +87,29 @@ def test_full_batch_equals_per_mesh_and_sampled_oracle(torch_cuda, meshes, mode)
     note(f"{mode}: every mesh equals its single call")
     if mode != "eft":
         return
+    # the per-pair schedule (every pair from its own endpoints) into a second set of outputs:
+    # the autotuned launch and the single calls share arc records on dense lists
+    scratch = None
+    second = [dict(m, out=sphint.Output(len(m["lat_idx"]))) for m in meshes]
+    plan = sphint.BatchPlan(second, mode="eft")
+    try:
+        plan.set_share(False)
+        plan.set_lookback(False)
+        plan.set_params(3, 0)
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.check()
+    finally:
+        plan.close()
+    for k, (m, s2) in enumerate(zip(meshes, second)):
+        o, r = m["out"], s2["out"]
+        t = int(o.total.item())
+        assert int(r.total.item()) == t, k
+        assert torch.equal(o.count, r.count) and torch.equal(o.flags, r.flags), k
+        for a, b in ((o.x, r.x), (o.y, r.y), (o.pair, r.pair), (o.root, r.root)):
+            assert torch.equal(a[:t], b[:t]), k
+    del second
+    note("eft: every mesh equals the per-pair schedule")
     # sampled pairs against the oracle
     rows, hits = [], []
     for k, q in picks[:400]:
