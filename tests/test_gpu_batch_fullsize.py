@@ -89,7 +89,7 @@ def test_full_batch_equals_per_mesh_and_sampled_oracle(torch_cuda, meshes, mode)
         return
     # the per-pair schedule (every pair from its own endpoints) into a second set of outputs:
     # the autotuned launch and the single calls share arc records on dense lists
-    scratch = None
+    scratch = None  # the single calls' outputs are freed before the second set is allocated
     second = [dict(m, out=sphint.Output(len(m["lat_idx"]))) for m in meshes]
     plan = sphint.BatchPlan(second, mode="eft")
     try:
