@@ -18,7 +18,8 @@ from paper_2510_09892_amd import build
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 FILES = ["tests/test_hostcheck.py", "tests/test_hostcheck_ablation.py",
          "tests/test_hostcheck_adaptive.py", "tests/test_hostcheck_arcarc.py",
-         "tests/test_hostcheck_property.py", "tests/test_candidates.py"]
+         "tests/test_hostcheck_property.py", "tests/test_hostcheck_shared.py",
+         "tests/test_candidates.py"]
 
 
 def test_host_build_is_clean_under_asan_and_ubsan(tmp_path):
