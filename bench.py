@@ -378,8 +378,8 @@ def batch_measure(torch, sphint, devs, stats, modes, steps, warmup):
         lb = plan.lookback()
         share = plan.share()
         kname = (f"graph launch: k_batch<{1 if mode == 'eft' else 0},{plan.params()[0]},true,"
-                 f"{'true' if lb else 'false'},{'true' if share else 'false'}> with its init and "
-                 f"pair-to-arc launches")
+                 f"{'true' if lb else 'false'},{'true' if share else 'false'}> with its init "
+                 f"launch (tile states, pair-to-arc tables)")
         roof = roofline(mode, {"kernel_ms": dms, "total": hits, "hitpairs": hitpairs}, nnz, byts,
                         kname, None, sum(st[1] for st in stats) if share else None)
         if share:
