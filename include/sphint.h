@@ -269,8 +269,9 @@ void sphint_plan_destroy(sphint_plan *plan);
  * device with the launch (as kernel arguments), so the call allocates nothing and does not
  * synchronise: an init kernel writes them into `workspace`, clears the tile states and
  * fills the CSR pair-to-arc tables, and the plan's persistent batched kernel follows on
- * `stream` (pairs per lane as in sphint_arc_constlat).  Each mesh's outputs equal a
- * sphint_arc_constlat call on that mesh alone.
+ * `stream` (pairs per lane as in sphint_arc_constlat; EFT launches over CSR lists holding
+ * at least 2.5 candidates per arc in all share arc records, as single calls do).  Each
+ * mesh's outputs equal a sphint_arc_constlat call on that mesh alone.
  *
  * workspace   device memory of at least sphint_batch_run_workspace_size(n_meshes, sum of
  *             the meshes' nnz) bytes, 256-byte aligned, used only by this launch while it

@@ -584,15 +584,17 @@ __global__ __launch_bounds__(INIT_BLOCK) void k_batch_run_init(const RunTable tb
 // Pairs per lane of a one-shot batch: those of single calls.
 constexpr int run_ppt(sphint_mode mode) { return mode == SPHINT_EFT_FP64 ? 3 : 4; }
 
-template <int MODE, bool CSR>
+// SHARE: EFT over CSR lists holding at least 2.5 candidates per arc in all (the single
+// call's rule), arc records shared among a tile's rows.
+template <int MODE, bool CSR, bool SHARE = false>
 void launch_run(const KArgs* d_args, const int64_t* d_base, int n, int64_t total_tiles,
                 hipStream_t st) {
   constexpr int PPT = MODE ? 3 : 4;
-  const int per_cu = max_resident<MODE, PPT, CSR>();
+  const int per_cu = max_resident<MODE, PPT, CSR, false, SHARE>();
   int64_t grid = (total_tiles + 1 + NWAVE - 1) / NWAVE;  // + the scanner
   if ((int64_t)per_cu * device_cus() < grid) grid = (int64_t)per_cu * device_cus();
-  hipLaunchKernelGGL((k_batch<MODE, PPT, CSR, false>), dim3((unsigned)grid), dim3(BLOCK), 0, st, d_args,
-                     d_base, n, total_tiles);
+  hipLaunchKernelGGL((k_batch<MODE, PPT, CSR, false, SHARE>), dim3((unsigned)grid), dim3(BLOCK),
+                     0, st, d_args, d_base, n, total_tiles);
 }
 
 }  // namespace
@@ -608,7 +610,7 @@ extern "C" sphint_status sphint_batch_run(const sphint_mesh_desc* meshes, int n_
   if (!meshes || n_meshes < 1 || n_meshes > RUN_MAX) return SPHINT_E_INVAL;
   if (mode != SPHINT_NAIVE_FP64 && mode != SPHINT_EFT_FP64) return SPHINT_E_INVAL;
   const bool csr = meshes[0].lat_offsets != nullptr;
-  int64_t total_nnz = 0;
+  int64_t total_nnz = 0, total_arcs = 0;
   for (int m = 0; m < n_meshes; ++m) {
     const sphint_mesh_desc& d = meshes[m];
     sphint_status v = validate(d.n_arcs, d.p1, d.p2, d.lat_z, d.n_lat, d.lat_offsets, d.lat_idx,
@@ -616,6 +618,7 @@ extern "C" sphint_status sphint_batch_run(const sphint_mesh_desc* meshes, int n_
     if (v != SPHINT_OK) return v;
     if ((d.lat_offsets != nullptr) != csr) return SPHINT_E_INVAL;
     total_nnz += d.nnz;
+    total_arcs += d.n_arcs;
   }
   if (total_nnz > ((int64_t)1 << 40)) return SPHINT_E_INVAL;
   if (!workspace || !aligned256(workspace) ||
@@ -656,7 +659,9 @@ extern "C" sphint_status sphint_batch_run(const sphint_mesh_desc* meshes, int n_
   if (hipGetLastError() != hipSuccess) return SPHINT_E_HIP;
   if (total_tiles > 0) {
     const bool eft = mode == SPHINT_EFT_FP64;
-    if (csr) eft ? launch_run<1, true>(d_args, d_base, n_meshes, total_tiles, st)
+    if (csr) eft ? (2 * total_nnz >= 5 * total_arcs
+                        ? launch_run<1, true, true>(d_args, d_base, n_meshes, total_tiles, st)
+                        : launch_run<1, true>(d_args, d_base, n_meshes, total_tiles, st))
                  : launch_run<0, true>(d_args, d_base, n_meshes, total_tiles, st);
     else eft ? launch_run<1, false>(d_args, d_base, n_meshes, total_tiles, st)
              : launch_run<0, false>(d_args, d_base, n_meshes, total_tiles, st);

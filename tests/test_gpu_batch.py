@@ -358,3 +358,43 @@ def test_batch_shared_arcs_equal_per_mesh(torch_cuda):
             naive.set_share(True)
     finally:
         naive.close()
+
+
+def test_batch_run_shared_arcs_equal_per_pair(torch_cuda):
+    """The one-shot batched launch over dense candidate lists (>= 2.5 candidates per arc in
+    all: arc records shared, EFT) equals the per-pair schedule of a plan, bit for bit, on
+    random meshes and the exact-tie mesh."""
+    import itertools
+    import math
+    import test_hostcheck_shared as TS
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    meshes = [inputs.random_mesh(inputs.rng(49, k), 2000 + 700 * k, 2500) for k in range(4)]
+    verts = [v for v in itertools.product((-1.0, 0.0, 1.0), repeat=3) if any(v)]
+    zs = []
+    for z in (-1.0, -0.5, 0.0, 0.375, 1.0, 0.7071067811865476):
+        zs += [z, math.nextafter(z, 2.0), math.nextafter(z, -2.0)]
+    meshes.append(_Mesh(*TS._csr([(*a, *b) for a in verts for b in verts],
+                                 [zs] * (len(verts) ** 2))))
+    assert 2 * sum(m.nnz for m in meshes) >= 5 * sum(len(m.lat_offsets) - 1 for m in meshes)
+    devs = [to_dev(torch, m) for m in meshes]
+    plan = sphint.BatchPlan(devs, mode="eft")
+    try:
+        plan.set_params(3, 0)  # per-pair schedule (sharing off by default)
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.check()
+        ref = [read(d["out"]) for d in devs]
+    finally:
+        plan.close()
+    assert any(np.any(r["flags"] & 32) for r in ref)
+    ws = torch.empty(sphint.batch_run_workspace_size(len(devs), sum(m.nnz for m in meshes)),
+                     dtype=torch.uint8, device="cuda")
+    for rep in range(2):
+        note(f"batch_run shared arcs, {len(devs)} meshes, round {rep}")
+        scrub(torch, devs)
+        sphint.batch_run(devs, mode="eft", workspace=ws)
+        torch.cuda.synchronize()
+        assert sphint.load().sphint_check(ws.data_ptr(), 0, 0) == sphint.OK
+        for k, (d, r) in enumerate(zip(devs, ref)):
+            assert same(read(d["out"]), r), (k, rep)
