@@ -52,7 +52,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   }
   int64_t t = gw;
   int mesh = 0;  // tiles only increase, so the mesh index only moves forward
-  wave_loop<MODE, PPT, CSR, flush_at<MODE, PPT>(), LB, SHARE>(args, sh, [&](int& m, int64_t& tile) {
+  wave_loop<MODE, PPT, CSR, flush_at<MODE, PPT, SHARE>(), LB, SHARE>(args, sh, [&](int& m, int64_t& tile) {
     if (t >= total_tiles) return false;
     while (mesh + 1 < n_meshes && tile_base[mesh + 1] <= t) ++mesh;
     m = mesh;

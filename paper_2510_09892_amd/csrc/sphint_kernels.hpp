@@ -753,12 +753,13 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
   }
 }
 
-// Rows evaluated before the previous tile is written out: one for the EFT evaluation
-// (registers are scarce, and a row takes long enough for the offset to arrive), the whole
-// tile for the short naive evaluation.
-template <int MODE, int WPPT>
+// Rows evaluated before the previous tile is written out, i.e. held in registers while the
+// scanner publishes that tile's offset: two for the EFT evaluation (one with shared arc
+// records, whose window already takes the registers), the whole tile for the short naive
+// evaluation.
+template <int MODE, int WPPT, bool SHARE = false>
 constexpr int flush_at() {
-  return MODE ? 1 : WPPT;
+  return MODE ? (SHARE || WPPT < 2 ? 1 : 2) : WPPT;
 }
 
 // Persistent wavefronts with a static order.  The grid never exceeds what the device holds
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     return;
   }
   int64_t t = gw;
-  wave_loop<MODE, WPPT, CSR, flush_at<MODE, WPPT>(), false, SHARE>(&a, sh, [&](int& m, int64_t& tile) {
+  wave_loop<MODE, WPPT, CSR, flush_at<MODE, WPPT, SHARE>(), false, SHARE>(&a, sh, [&](int& m, int64_t& tile) {
     if (t >= a.ntiles) return false;
     m = 0;
     tile = t;
