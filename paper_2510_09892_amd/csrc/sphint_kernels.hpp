@@ -305,6 +305,7 @@ struct TileRegs {
   PairOut o[WPPT];
   int woff[WPPT];
   int agg;
+  bool err;  // an exact sign overflowed its arena (reported once per tile)
 };
 
 // Inputs of one row (64 pairs, one per lane) of a tile; `o` is the pair's offset in the
@@ -313,7 +314,7 @@ struct RowIn {
   double x1, y1, z1, x2, y2, z2, z0;
   int64_t arc;  // CSR: the pair's arc (clamped); rows evaluated from shared arc records
                 // load only this, not the endpoints
-  uint32_t o;
+  uint32_t o, oc;  // offset in the tile, offset read (the last pair's for lanes past the end)
   bool valid;
 };
 
@@ -330,23 +331,58 @@ __device__ __forceinline__ TileCtx tile_ctx(const KArgs& a, int64_t tile) {
   return c;
 }
 
-// Loads one row without branches: lanes past the end read the last pair (and are marked
-// invalid), so the compiler can count outstanding loads exactly and the row fetched ahead
-// stays in flight while the current row is evaluated.  CSR calls take each pair's arc from
-// the pair-to-arc table that the init launch wrote (clamped, so malformed offsets cannot send
-// a read out of bounds).
-template <bool CSR, bool SHARE = false>
-__device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int j) {
-  RowIn r;
-  // offsets stay below 1024 (a tile has at most 1024 pairs); the mask tells the compiler
-  // so, which lets it address from a scalar base plus a 32-bit lane offset
-  r.o = (uint32_t)(j * 64 + __lane_id()) & 1023u;
-  r.valid = c.base + (int64_t)r.o < a.nnz;
-  const uint32_t oc = (r.valid ? r.o : (uint32_t)(a.nnz - 1 - c.base)) & 1023u;
+// A row's slot: lane l holds pair j * 64 + l of the tile; lanes past the end read the last
+// pair (and are marked invalid), so every load is unconditional and the compiler can count
+// outstanding loads exactly.  Offsets stay below 1024 (a tile has at most 1024 pairs); the
+// mask tells the compiler so, which lets it address from a scalar base plus a 32-bit lane
+// offset.
+struct RowSlot {
+  uint32_t o, oc;  // offset in the tile, offset read
+  bool valid;
+};
+
+__device__ __forceinline__ RowSlot row_slot(const KArgs& a, const TileCtx& c, int j) {
+  RowSlot s;
+  s.o = (uint32_t)(j * 64 + __lane_id()) & 1023u;
+  s.valid = c.base + (int64_t)s.o < a.nnz;
+  s.oc = (s.valid ? s.o : (uint32_t)(a.nnz - 1 - c.base)) & 1023u;
+  return s;
+}
+
+// First level of a CSR row's loads: each pair's arc, from the pair-to-arc table that the
+// init launch wrote, and its latitude index.  The gathers that depend on them (latitude,
+// endpoints) are the second level, load_row; splitting the two lets a wavefront issue a
+// row's first level one row before its second, so neither waits on the other.
+struct RowIdx {
+  uint32_t arc;
+  int32_t li;
+};
+
+template <bool CSR>
+__device__ __forceinline__ RowIdx load_idx(const KArgs& a, const TileCtx& c, int j) {
+  RowIdx x = {0u, 0};
   if (CSR) {
-    const int64_t pa = (int64_t)gptr(a.parc + c.base)[oc];
+    const RowSlot s = row_slot(a, c, j);
+    x.arc = gptr(a.parc + c.base)[s.oc];
+    x.li = gptr(a.idx + c.base)[s.oc];
+  }
+  return x;
+}
+
+// Loads one row (CSR: the second level, from the row's first-level values x; both are
+// clamped, so malformed offsets or indices cannot send a read out of bounds).
+template <bool CSR, bool SHARE = false>
+__device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int j,
+                                          const RowIdx& x) {
+  RowIn r;
+  const RowSlot s = row_slot(a, c, j);
+  r.o = s.o;
+  r.oc = s.oc;
+  r.valid = s.valid;
+  if (CSR) {
+    const int64_t pa = (int64_t)x.arc;
     const int64_t arc = pa < a.n_arcs ? pa : a.n_arcs - 1;
-    const int32_t li = gptr(a.idx + c.base)[oc];
+    const int32_t li = x.li;
     const bool ok = li >= 0 && li < a.n_lat;
     const double z = gptr(a.lat_z)[ok ? li : 0];
     r.z0 = ok ? z : __builtin_nan("");
@@ -356,12 +392,18 @@ __device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int 
       r.x2 = gptr(a.x2)[arc]; r.y2 = gptr(a.y2)[arc]; r.z2 = gptr(a.z2)[arc];
     }
   } else {
+    const uint32_t oc = s.oc;
     r.z0 = gptr(a.lat_z + c.base)[oc];
     r.x1 = gptr(a.x1 + c.base)[oc]; r.y1 = gptr(a.y1 + c.base)[oc];
     r.z1 = gptr(a.z1 + c.base)[oc]; r.x2 = gptr(a.x2 + c.base)[oc];
     r.y2 = gptr(a.y2 + c.base)[oc]; r.z2 = gptr(a.z2 + c.base)[oc];
   }
   return r;
+}
+
+template <bool CSR, bool SHARE = false>
+__device__ __forceinline__ RowIn load_row(const KArgs& a, const TileCtx& c, int j) {
+  return load_row<CSR, SHARE>(a, c, j, load_idx<CSR>(a, c, j));
 }
 
 // CSR pair-to-arc table: parc[k] = the arc owning entry k.  Wavefront w of nw takes
@@ -420,6 +462,19 @@ __device__ __forceinline__ void fill_pair_arcs(const int64_t* __restrict__ off, 
   }
 }
 
+// Writes a row's counts and flags.  Every lane stores, so that the compiler can count the
+// row's memory operations exactly and later waits for loads need not wait for these stores:
+// a lane past the end holds the last pair (read at its slot `oc`), evaluated like the lane
+// that owns it, so it writes the same bytes there.  Without a flags array the flags go to the
+// count's byte first, and the count overwrites them (one lane's stores to one address stay
+// in program order).
+__device__ __forceinline__ void store_row(const KArgs& a, const TileCtx& c, const RowIn& in,
+                                          const PairOut& o) {
+  uint8_t* const fl = a.oflags ? a.oflags : a.ocount;
+  gptr(fl + c.base)[in.oc] = (uint8_t)o.flags;
+  gptr(a.ocount + c.base)[in.oc] = (uint8_t)o.count;
+}
+
 // Evaluates one row already loaded, writes its counts and flags, and accumulates the
 // tile's in-order hit offsets.
 template <int MODE, int WPPT, class Shared>
@@ -429,7 +484,7 @@ __device__ __forceinline__ void eval_row(const KArgs& a, const TileCtx& c, const
   const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   PairOut& o = r.o[j];
   if (MODE) {
-    o = eval_eft(in.valid, in.x1, in.y1, in.z1, in.x2, in.y2, in.z2, in.z0, sh.arena,
+    o = eval_eft(true, in.x1, in.y1, in.z1, in.x2, in.y2, in.z2, in.z0, sh.arena,
                  [&](bool need, auto&& fn) {
                    resolve_serial(need, [&] {
                      lds_lock(&sh.lock);
@@ -437,18 +492,16 @@ __device__ __forceinline__ void eval_row(const KArgs& a, const TileCtx& c, const
                      lds_unlock(&sh.lock);
                    });
                  });
-    if (o.flags & F_INTERNAL) atomicOr(a.ws + 1, ERR_EXACT);
   } else {
-    o = eval_naive(in.valid, in.x1, in.y1, in.z1, in.x2, in.y2, in.z2, in.z0);
+    o = eval_naive(true, in.x1, in.y1, in.z1, in.x2, in.y2, in.z2, in.z0);
   }
+  store_row(a, c, in, o);
   const int cnt = in.valid ? o.count : 0;
   o.count = cnt;
-  if (in.valid) {
-    gptr(a.ocount + c.base)[in.o] = (uint8_t)cnt;
-    if (a.oflags) gptr(a.oflags + c.base)[in.o] = (uint8_t)o.flags;
-  }
   const unsigned long long b1 = __ballot(cnt >= 1);
   const unsigned long long b2 = __ballot(cnt >= 2);
+  const bool err = (o.flags & F_INTERNAL) != 0;
+  r.err = j == 0 ? err : r.err || err;
   if (j == 0) r.agg = 0;
   r.woff[j] = r.agg + __popcll(b1 & lt) + __popcll(b2 & lt);
   r.agg += __popcll(b1) + __popcll(b2);
@@ -599,7 +652,8 @@ __device__ __forceinline__ void eval_row_shared(const KArgs& a, int m, const Til
       },
       D.S2, in.z0, S, q);
   if (o.count) o = q;
-  if (o.flags & F_INTERNAL) atomicOr(a.ws + 1, ERR_EXACT);
+  // only valid lanes store here: the window fills already leave the compiler unsure how many
+  // memory operations a row issues, so unconditional stores would gain nothing
   const int cnt = in.valid ? o.count : 0;
   o.count = cnt;
   if (in.valid) {
@@ -608,6 +662,8 @@ __device__ __forceinline__ void eval_row_shared(const KArgs& a, int m, const Til
   }
   const unsigned long long b1 = __ballot(cnt >= 1);
   const unsigned long long b2 = __ballot(cnt >= 2);
+  const bool err = (o.flags & F_INTERNAL) != 0;
+  r.err = j == 0 ? err : r.err || err;
   if (j == 0) r.agg = 0;
   r.woff[j] = r.agg + __popcll(b1 & lt) + __popcll(b2 & lt);
   r.agg += __popcll(b1) + __popcll(b2);
@@ -670,7 +726,8 @@ __device__ __forceinline__ int64_t tile_prefix(const KArgs& a, int64_t tile, int
 
 // One wavefront's share of the tiles: tiles come from `next` (the KArgs index and local
 // tile, or false when done).  Loads run one row ahead of evaluation (the next tile's first
-// row is fetched while the current tile's last row is evaluated).  A tile's hit count is
+// row is fetched while the current tile's last row is evaluated); a CSR row's first-level
+// loads run two rows ahead.  A tile's hit count is
 // published when its last row is done; the previous tile's hits are written out after the
 // first FLUSH_AT rows of the next tile, which gives the scanner that much time to publish
 // its offset.  Rows evaluated after that point go straight to the staging buffer, so at most
@@ -694,25 +751,50 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
   m = __builtin_amdgcn_readfirstlane(m);  // wavefront-uniform: the arguments load as scalars
   TileCtx ctx = tile_ctx<WPPT, CSR>(args[m], tile), ctx2;
   RowIn cur = load_row<CSR, SHARE>(args[m], ctx, 0), nxt;
+  // CSR rows with two or more rows per tile: the first-level loads of the row after the
+  // next one (ix) are in flight while the next row's gathers are issued from the values
+  // loaded a row earlier.  Not with shared arc records below four rows per tile: those
+  // kernels sit at the register limit of four wavefronts per SIMD, where the extra row in
+  // flight spills.
+  constexpr bool PIPE = CSR && WPPT >= 2 && (!SHARE || WPPT >= 4);
+  RowIdx ix = load_idx<PIPE>(args[m], ctx, 1);
   ArcWin win;
   win.base = 0;
   win.mesh = -1;
+  // the next tile, fetched one row before the end of this one (PIPE) or at its last row;
+  // past the last tile the fetches repeat this tile (unused)
+  auto fetch_tile = [&]() {
+    const bool h = next(m2, tile2);
+    if (!h) {
+      m2 = m;
+      tile2 = tile;
+    }
+    m2 = __builtin_amdgcn_readfirstlane(m2);
+    ctx2 = tile_ctx<WPPT, CSR>(args[m2], tile2);
+    return h;
+  };
   while (have) {
     const KArgs& a = args[m];
     bool have2 = false;
 #pragma unroll
     for (int j = 0; j < WPPT; ++j) {
-      if (j + 1 < WPPT) {
+      if constexpr (PIPE) {
+        if (j + 1 < WPPT)
+          nxt = load_row<CSR, SHARE>(a, ctx, j + 1, ix);
+        else
+          nxt = load_row<CSR, SHARE>(args[m2], ctx2, 0, ix);
+        if (j + 2 < WPPT) {
+          ix = load_idx<CSR>(a, ctx, j + 2);
+        } else if (j + 2 == WPPT) {
+          have2 = fetch_tile();
+          ix = load_idx<CSR>(args[m2], ctx2, 0);
+        } else {
+          ix = load_idx<CSR>(args[m2], ctx2, 1);
+        }
+      } else if (j + 1 < WPPT) {
         nxt = load_row<CSR, SHARE>(a, ctx, j + 1);
       } else {
-        // always fetch ahead; past the last tile the fetch repeats this tile (unused)
-        have2 = next(m2, tile2);
-        if (!have2) {
-          m2 = m;
-          tile2 = tile;
-        }
-        m2 = __builtin_amdgcn_readfirstlane(m2);
-        ctx2 = tile_ctx<WPPT, CSR>(args[m2], tile2);
+        have2 = fetch_tile();
         nxt = load_row<CSR, SHARE>(args[m2], ctx2, 0);
       }
       if constexpr (SHARE)
@@ -737,6 +819,7 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
     if (__lane_id() == 0)
       __hip_atomic_store(a.status + tile, ((uint64_t)r.agg << 2) | ST_AGG, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
+    if (MODE && __ballot(r.err) && __lane_id() == 0) atomicOr(a.ws + 1, ERR_EXACT);
     pending = true;
     pm = m;
     ptile = tile;

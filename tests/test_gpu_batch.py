@@ -298,6 +298,46 @@ def shared_arc_meshes():
     return meshes
 
 
+@pytest.mark.parametrize("mode", ["eft", "naive"])
+def test_batch_without_flags_arrays(torch_cuda, mode):
+    """Meshes without flags arrays (their flags go to the count bytes first, then the
+    counts): every schedule gives the per-mesh calls' counts and hits."""
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    meshes = make_meshes(4, seed_tag=47)
+    devs = [to_dev(torch, m) for m in meshes]
+    ref = per_mesh(torch, devs, mode)
+    for d in devs:
+        d["out"] = sphint.Output(d["out"].nnz, flags=False)
+    plan = sphint.BatchPlan(devs, mode=mode)
+    shares = (False, True) if mode == "eft" else (False,)
+    try:
+        for share in shares:
+            if mode == "eft":
+                plan.set_share(share)
+            for lb in (False, True):
+                plan.set_lookback(lb)
+                for ppt in ((1, 2, 3, 4, 5) if share else (1, 2, 3, 4)):
+                    note(f"{mode} without flags: ppt={ppt} lookback={lb} share={share}")
+                    plan.set_params(ppt, 0)
+                    for d in devs:
+                        d["out"].count.fill_(255)
+                        d["out"].total.fill_(-1)
+                    plan.launch()
+                    torch.cuda.synchronize()
+                    plan.check()
+                    for d, r in zip(devs, ref):
+                        o = d["out"]
+                        t = int(o.total.item())
+                        assert t == r["total"], (ppt, lb, share)
+                        assert np.array_equal(o.count.cpu().numpy(), r["count"])
+                        for key, a in (("x", o.x), ("y", o.y), ("pair", o.pair), ("root", o.root)):
+                            assert np.array_equal(a[:t].cpu().numpy().view(np.uint8),
+                                                  r[key].view(np.uint8)), (key, ppt, lb, share)
+    finally:
+        plan.close()
+
+
 def test_batch_shared_arcs_equal_per_mesh(torch_cuda):
     """EFT plans over CSR lists with arc records shared by a tile's rows: every schedule
     (pairs per lane x scanner or look-back x workgroups per CU), and every single call, gives

@@ -259,6 +259,57 @@ def test_csr_dense_candidates_shared_arcs(torch_cuda):
     check_eft(res, t.expand().soa())
 
 
+def _outputs(torch, call, nnz, flags):
+    from paper_2510_09892_amd import sphint
+    out = sphint.Output(nnz, flags=flags)
+    call(out)
+    torch.cuda.synchronize()
+    t = out.check()
+    return dict(total=t, count=out.count.cpu().numpy(), x=out.x[:t].cpu().numpy(),
+                y=out.y[:t].cpu().numpy(), pair=out.pair[:t].cpu().numpy(),
+                root=out.root[:t].cpu().numpy(),
+                flags=out.flags.cpu().numpy() if flags else None)
+
+
+@pytest.mark.parametrize("mode", ["eft", "naive"])
+def test_without_flags_array(torch_cuda, mode):
+    """A call without a flags array gives the counts and hits of a call with one (the
+    kernels then write each pair's flags into its count byte before the count).  Ragged
+    sizes whose last tile ends in rows past the last pair, with a two-hit pair last: lanes
+    past the end hold that pair and write its bytes too.  Dense, CSR, and CSR with shared
+    arc records."""
+    from paper_2510_09892_amd import sphint
+    torch = torch_cuda
+    P = inputs.ill_conditioned(20_011, seed_tag=111)
+    soa = [np.ascontiguousarray(a) for a in P.soa()]
+    first = gpu_dense(torch, soa, mode)
+    k = int(np.flatnonzero(first["count"] == 2)[0])
+    for a in soa:
+        a[-1] = a[k]  # the last pair has two hits
+    dev = to_dev(torch, soa)
+
+    def dense(out):
+        sphint.arc_constlat(tuple(dev[:3]), tuple(dev[3:6]), dev[6], mode=mode, out=out)
+    cases = [("dense", dense, len(soa[0]))]
+    for tag, m in (("csr", inputs.random_mesh(inputs.rng(112), 3001, 300, d_hi=0.05)),
+                   ("csr shared", inputs.random_mesh(inputs.rng(113), 701, 3000, d_hi=0.05))):
+        d = to_dev(torch, (*m.soa(), m.lat_z, m.lat_offsets, m.lat_idx))
+
+        def csr(out, d=d):
+            sphint.arc_constlat(tuple(d[:3]), tuple(d[3:6]), d[6], d[7], d[8], mode=mode,
+                                out=out)
+        cases.append((tag, csr, m.nnz))
+    for tag, call, nnz in cases:
+        note(f"without flags: {tag} {mode} nnz={nnz}")
+        a = _outputs(torch, call, nnz, True)
+        b = _outputs(torch, call, nnz, False)
+        assert a["total"] == b["total"]
+        for key in ("count", "x", "y", "pair", "root"):
+            assert np.array_equal(a[key].view(np.uint8), b[key].view(np.uint8)), (tag, key)
+        if tag == "dense":
+            assert a["count"][-1] == 2 and b["count"][-1] == 2
+
+
 def test_csr_bad_latitude_index_is_flagged(torch_cuda):
     m = inputs.random_mesh(inputs.rng(108), 200, 50)
     m.lat_idx[::7] = 10_000          # out of range: must become NONFINITE, not an OOB read
