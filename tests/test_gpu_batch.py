@@ -9,6 +9,7 @@
 * Graph replays, with eager work and synchronisations between them, all give the same
   bytes; the autotuner's cache file is written and read back.
 * One small mesh against the oracle.
+* Meshes without flags arrays: every schedule gives the per-mesh counts and hits.
 * The one-shot batched launch (sphint_batch_run, no plan) over 1, 7 and 16 meshes (CSR
   with an empty mesh among them, and dense), reusing one workspace on one stream: every
   mesh equals its single call, in both modes.
