@@ -125,4 +125,45 @@ __host__ __device__ __forceinline__ dd acc_sqrt(double a, double e) {
   return fast_two_sum(sh, sl);
 }
 
+// Quotients n / d over one denominator d, each the correctly rounded binary64 quotient.
+// On the GPU the division sequence the compiler emits (reciprocal estimate, two Newton steps
+// on the reciprocal, the product and one FMA correction) is split: its reciprocal part
+// depends on d alone and runs once, and each numerator takes the product and its
+// corrections (three operations instead of eleven).  The split sequence is the compiled one
+// whenever that one would not rescale its operands: d and |n| within [2^-380, 2^380] keep
+// the operands, the quotient and every intermediate normal with exponents less than 768
+// apart.  Other operands take the ordinary division, as does the CPU build.
+struct Divider {
+  double d, r;
+  bool ok;
+};
+
+__host__ __device__ __forceinline__ Divider divider(double d) {
+  Divider v;
+  v.d = d;
+#if defined(__HIP_DEVICE_COMPILE__)
+  v.ok = d >= 0x1p-380 && d <= 0x1p380;
+  const double r0 = __builtin_amdgcn_rcp(d);
+  const double r1 = __builtin_fma(r0, __builtin_fma(-d, r0, 1.0), r0);
+  v.r = __builtin_fma(r1, __builtin_fma(-d, r1, 1.0), r1);
+  // computed here once: without this the compiler recomputes it inside every quotient
+  __asm__ volatile("" : "+v"(v.r));
+#else
+  v.ok = false;
+  v.r = 0.0;
+#endif
+  return v;
+}
+
+__host__ __device__ __forceinline__ double quot(const Divider& v, double n) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double a = __builtin_fabs(n);
+  if (v.ok && a >= 0x1p-380 && a <= 0x1p380) {
+    const double m = n * v.r;
+    return __builtin_fma(__builtin_fma(-v.d, m, n), v.r, m);
+  }
+#endif
+  return n / v.d;
+}
+
 }  // namespace sphint

@@ -333,6 +333,7 @@ template <class G>
 __host__ __device__ __forceinline__ void points_eft_g(G&& g, double S2, double z0,
                                                       const S2Eft& s2, PairOut& o) {
   const dd sq = acc_sqrt(s2.ss, s2.ess);
+  const Divider dv = divider(S2);
   const CdState hx = comp_dot_head(two_prod(g(0), z0), two_prod(g(1), z0));
   const CdState hy = comp_dot_head(two_prod(g(2), z0), two_prod(g(3), z0));
   const bool plus0 = o.r0 == ROOT_PLUS;
@@ -342,15 +343,15 @@ __host__ __device__ __forceinline__ void points_eft_g(G&& g, double S2, double z
     const double ny = g(6), eny = g(7);
     const dd x2 = two_prod(ny, sb), x3 = two_prod(eny, sb);
     const dd x4 = two_prod(ny, es), x5 = two_prod(eny, es);
-    o.px0 = -(comp_dot_tail(hx, x2, x3, x4, x5, 1.0) / S2);
-    if (o.count == 2) o.px1 = -(comp_dot_tail(hx, x2, x3, x4, x5, -1.0) / S2);
+    o.px0 = -quot(dv, comp_dot_tail(hx, x2, x3, x4, x5, 1.0));
+    if (o.count == 2) o.px1 = -quot(dv, comp_dot_tail(hx, x2, x3, x4, x5, -1.0));
   }
   {
     const double nx = g(4), enx = g(5);
     const dd y2 = two_prod(-nx, sb), y3 = two_prod(-enx, sb);
     const dd y4 = two_prod(-nx, es), y5 = two_prod(-enx, es);
-    o.py0 = -(comp_dot_tail(hy, y2, y3, y4, y5, 1.0) / S2);
-    if (o.count == 2) o.py1 = -(comp_dot_tail(hy, y2, y3, y4, y5, -1.0) / S2);
+    o.py0 = -quot(dv, comp_dot_tail(hy, y2, y3, y4, y5, 1.0));
+    if (o.count == 2) o.py1 = -quot(dv, comp_dot_tail(hy, y2, y3, y4, y5, -1.0));
   }
 }
 
