@@ -132,6 +132,25 @@ def _edge_soa():
     return [a[:, k].copy() for k in range(7)]
 
 
+def test_dense_power_of_two_scaling(torch_cuda):
+    """The EFT arithmetic commutes with scaling the endpoints by powers of two as long as
+    nothing underflows or overflows, so scaled inputs give the unscaled results bit for bit.
+    The scales move |n_xy|^2 from about 2^-320 to 2^600, on both sides of the range where
+    the point divisions take their shared-reciprocal form (inside 2^+-380) and where they
+    divide directly."""
+    P = inputs.ill_conditioned(9_001, seed_tag=114)
+    soa = [np.ascontiguousarray(a) for a in P.soa()]
+    base = gpu_dense(torch_cuda, soa, "eft")
+    assert base["total"] > 0
+    for k1, k2 in ((-80, -80), (-200, -100), (150, 150), (-120, 60)):
+        note(f"power-of-two scaling 2^{k1}, 2^{k2}")
+        sc = [a * 2.0 ** k1 for a in soa[:3]] + [a * 2.0 ** k2 for a in soa[3:6]] + [soa[6]]
+        res = gpu_dense(torch_cuda, sc, "eft")
+        assert res["total"] == base["total"], (k1, k2)
+        for key in ("count", "flags", "x", "y", "pair", "root"):
+            assert np.array_equal(res[key].view(np.uint8), base[key].view(np.uint8)), (k1, k2, key)
+
+
 def test_dense_edge_cases(torch_cuda):
     """Exact ties, tangencies, degenerate and non-finite inputs (exact expansions path)."""
     soa = _edge_soa()

@@ -246,6 +246,10 @@ def test_metamorphic_relations_bit_exact(hc, mode):
         assert np.array_equal(r0[hit & nt], 1 - m0[hit & nt])
         assert np.array_equal(r1[two], 1 - m1[two])
         if mode == 1:
-            scaled = run(hc, mode, (8 * x1, 8 * y1, 8 * z1, x2, y2, z2, z0))
-            for u, v in zip((cnt, fl, r0, r1, px0, py0, px1, py1), scaled):
-                assert np.array_equal(u, v)
+            # from a factor 8 to factors that move |n_xy|^2 by 2^-600 and 2^600 (nothing
+            # underflows or overflows on this workload)
+            for k1, k2 in ((3, 0), (-80, -80), (-200, -100), (150, 150), (-120, 60)):
+                s1, s2 = 2.0 ** k1, 2.0 ** k2
+                scaled = run(hc, mode, (s1 * x1, s1 * y1, s1 * z1, s2 * x2, s2 * y2, s2 * z2, z0))
+                for u, v in zip((cnt, fl, r0, r1, px0, py0, px1, py1), scaled):
+                    assert np.array_equal(u, v), (k1, k2)
