@@ -837,12 +837,11 @@ __device__ __forceinline__ void wave_loop(const KArgs* args, WgShared<MODE, WPPT
 }
 
 // Rows evaluated before the previous tile is written out, i.e. held in registers while the
-// scanner publishes that tile's offset: two for the EFT evaluation (one with shared arc
-// records, whose window already takes the registers), the whole tile for the short naive
-// evaluation.
+// scanner publishes that tile's offset: two (one with shared arc records, whose window
+// already takes the registers, and in one-row tiles).
 template <int MODE, int WPPT, bool SHARE = false>
 constexpr int flush_at() {
-  return MODE ? (SHARE || WPPT < 2 ? 1 : 2) : WPPT;
+  return (MODE && SHARE) || WPPT < 2 ? 1 : 2;
 }
 
 // Persistent wavefronts with a static order.  The grid never exceeds what the device holds
