@@ -114,11 +114,31 @@ __host__ __device__ __forceinline__ dd f_pair(double na, double ena, double nz, 
   return {f.hi, (f.lo + e2) + e3};
 }
 
+// The correctly rounded square root of a > 0.  On the GPU, for a within [2^-700, 2^700],
+// the square-root sequence the compiler emits without its range steps (the reciprocal square
+// root estimate and four FMA refinements; the scaling of tiny arguments and the zero and
+// infinity fix-up are idle there), else the full one, as on the CPU.
+__host__ __device__ __forceinline__ double sqrt_pos(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (a >= 0x1p-700 && a <= 0x1p700) {
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y;
+    double h = y * 0.5;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    g = __builtin_fma(__builtin_fma(-g, g, a), h, g);
+    return __builtin_fma(__builtin_fma(-g, g, a), h, g);
+  }
+#endif
+  return __builtin_sqrt(a);
+}
+
 // AccSqrt of the pair (a, e), |e| <= u a: double-word square root with one first-order
 // correction and a FastTwoSum renormalisation (relative error 25/8 u^2).
 __host__ __device__ __forceinline__ dd acc_sqrt(double a, double e) {
   if (!(a > 0.0)) return {0.0, 0.0};
-  double sh = __builtin_sqrt(a);
+  double sh = sqrt_pos(a);
   double rho1 = __builtin_fma(-sh, sh, a);
   double rho2 = rho1 + e;
   double sl = rho2 / (2.0 * sh);
