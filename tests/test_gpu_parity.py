@@ -151,6 +151,24 @@ def test_dense_power_of_two_scaling(torch_cuda):
             assert np.array_equal(res[key].view(np.uint8), base[key].view(np.uint8)), (k1, k2, key)
 
 
+def test_csr_power_of_two_scaling(torch_cuda):
+    """The same invariance for CSR calls, per-pair and with shared arc records (whose window
+    records then hold scaled normals): scaled endpoints give the unscaled bytes."""
+    for tag, m in (("per-pair", inputs.random_mesh(inputs.rng(116), 3001, 300, d_hi=0.05)),
+                   ("shared", inputs.random_mesh(inputs.rng(117), 701, 3000, d_hi=0.05))):
+        base = gpu_csr(torch_cuda, m, "eft")
+        assert base["total"] > 0
+        for k1, k2 in ((-200, -100), (150, 150), (-90, -70)):
+            note(f"csr {tag} power-of-two scaling 2^{k1}, 2^{k2}")
+            sc = inputs.CsrMesh(m.p1 * 2.0 ** k1, m.p2 * 2.0 ** k2, m.lat_z, m.lat_offsets,
+                                m.lat_idx)
+            res = gpu_csr(torch_cuda, sc, "eft")
+            assert res["total"] == base["total"], (tag, k1, k2)
+            for key in ("count", "flags", "x", "y", "pair", "root"):
+                assert np.array_equal(res[key].view(np.uint8), base[key].view(np.uint8)), \
+                    (tag, k1, k2, key)
+
+
 def test_dense_edge_cases(torch_cuda):
     """Exact ties, tangencies, degenerate and non-finite inputs (exact expansions path)."""
     soa = _edge_soa()
